@@ -1,0 +1,153 @@
+/*
+ * mtp.h - C ABI of the MI355X Moment Tensor Potential library (libmtp.so).
+ *
+ * The library evaluates the Moment Tensor Potential, the model the paper
+ * accelerates inside LAMMPS (Section 2.1: inference yields energies, forces
+ * and stresses; active learning adds an extrapolation grade in neighbourhood
+ * or configuration mode).  The potential itself is defined by the MTP
+ * formulation the paper cites in Section 1:
+ *
+ *   u       = (2 r - (r_min + r_cut)) / (r_cut - r_min)
+ *   Q_b(r)  = T_b(u) (r_cut - r)^2                   Chebyshev T_b, b < n_cheb
+ *   f_mu    = sum_b c[z_i][z_j][mu][b] Q_b(r_ij)
+ *   M_mu,nu = sum_j f_mu(r_ij) d_ij^(x nu)           d_ij = R_j + n.H - R_i (full vector)
+ *   B_alpha = full contraction of moments (every contraction multigraph of level <= L,
+ *             moment level 2 + 4 mu + nu, disconnected products included)
+ *   E_i     = s[z_i] + sum_alpha xi_alpha B_alpha(i),  E = sum_i E_i
+ *   F_k     = -dE/dR_k,   W = -sum_{i,j} d_ij (x) dE_i/dd_ij
+ *   grade_i = max_k |sum_alpha B_alpha(i) Ainv[alpha][k]|
+ *
+ * Conventions shared by every call:
+ *   - Device pointers are caller-owned device memory (for instance torch
+ *     tensors); host pointers are said to be host.  Arrays are C-contiguous.
+ *   - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *     Work is enqueued on it; calls return before the GPU finishes unless a
+ *     call says it synchronizes.
+ *   - Every call returns an MTP_* status and never aborts; mtp_last_error()
+ *     gives a message for the calling thread.
+ *   - A handle is not thread-safe; use one handle per stream.
+ *   - The basis order (index alpha of the linear coefficients) is: total
+ *     level, then moment labels (mu, nu) sorted ascending, then the smallest
+ *     row-major upper-triangle tuple of the contraction matrix.
+ */
+#ifndef MTP_H
+#define MTP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MTP_OK 0
+#define MTP_ERR_ARG 1         /* invalid argument (null pointer, bad size, species out of range) */
+#define MTP_ERR_CELL 2        /* singular cell, or a shift outside the packed range */
+#define MTP_ERR_CAPACITY 3    /* caller buffer too small; the required size is reported */
+#define MTP_ERR_NONFINITE 4   /* a non-finite position was found */
+#define MTP_ERR_HIP 5         /* a HIP runtime call failed */
+#define MTP_ERR_OOM 6         /* device allocation failed */
+#define MTP_ERR_LEVEL 7       /* this level is not compiled into the library */
+#define MTP_GRADE_BREAK 8     /* grade_max exceeded grade_break; outputs are still written */
+#define MTP_GRADE_SELECT 9    /* grade_max exceeded grade_select (but not grade_break) */
+
+/* precision of the moment/contraction arithmetic */
+#define MTP_FP64 0            /* everything in binary64 */
+#define MTP_FP32_MOMENTS 1    /* radial functions, moments, contractions and pair gradients in
+                                 binary32; displacements, energies, virial and force sums in binary64 */
+
+/* grade product */
+#define MTP_GRADE_FP64 0      /* B . Ainv on binary64 matrix cores */
+#define MTP_GRADE_FP32SPLIT 1 /* hi/lo binary32 split, three binary32 matrix-core products,
+                                 binary64 accumulation of the tile partials */
+
+typedef struct mtp_model mtp_model;
+
+typedef struct {
+  int level;             /* MTP level L (even, compiled set reported by mtp_levels) */
+  int n_species;         /* number of species, >= 1 */
+  int n_cheb;            /* Chebyshev basis size n_cheb, 1..16 */
+  double r_min, r_cut;   /* radial interval (Angstrom), 0 <= r_min < r_cut */
+  const double* radial;  /* host [n_species][n_species][n_mu][n_cheb], c[z_i][z_j][mu][b] */
+  const double* linear;  /* host [n_alpha], xi in the basis order above */
+  const double* shift;   /* host [n_species], per-species energy constant s */
+  int precision;         /* MTP_FP64 or MTP_FP32_MOMENTS */
+  int chunk_atoms;       /* atoms evaluated per chunk (bounds workspace, cf. the paper's
+                            chunksize, Section 2.3); 0 = library default */
+  double grade_select;   /* grade_max above this returns MTP_GRADE_SELECT; <= 0 disables */
+  double grade_break;    /* grade_max above this returns MTP_GRADE_BREAK; <= 0 disables */
+} mtp_params;
+
+typedef struct {
+  int n_atoms;           /* N >= 0 */
+  const double* pos;     /* device [N][3] Cartesian positions, used as given (not wrapped) */
+  const int* species;    /* device [N], values in [0, n_species) */
+  double cell[9];        /* host copy of H, rows are the lattice vectors (row-major) */
+} mtp_system;
+
+/* Canonical full neighbour list in CSR form (all device memory).
+ * Row i holds every (j, n) with 0 < |R_j - R_i + n.H|^2 < r_cut^2, j = i allowed when n != 0,
+ * sorted by (j, n1, n2, n3).  The squared distance is evaluated in binary64 round-to-nearest
+ * without fused multiply-add as
+ *     t_a = (n1 H[0][a] + n2 H[1][a]) + n3 H[2][a],  d_a = (R_j[a] - R_i[a]) + t_a,
+ *     dd  = (d_0 d_0 + d_1 d_1) + d_2 d_2,  test dd < r_cut * r_cut.
+ * shift packs n: byte k (k = 0, 1, 2) holds n_{k+1} as a two's-complement int8.
+ * rev[p] is the index of the mirrored pair (j, i, -n). */
+typedef struct {
+  const int* off;        /* [N + 1] */
+  const int* j;          /* [n_pairs] */
+  const int* shift;      /* [n_pairs] */
+  const int* rev;        /* [n_pairs] */
+  long long n_pairs;
+} mtp_nlist;
+
+/* Number of compiled levels and their values (host array of at least 32 ints). */
+int mtp_levels(int* n, int* levels);
+
+/* Create a model: copies the parameters to the device.  Synchronizes. */
+int mtp_create(const mtp_params* p, mtp_model** out);
+void mtp_destroy(mtp_model* m);
+const char* mtp_last_error(void);
+
+/* Sizes of the model: basis functions, radial functions, stored moment components,
+ * connected contractions (any pointer may be NULL). */
+int mtp_sizes(const mtp_model* m, int* n_alpha, int* n_mu, int* n_moments, int* n_components);
+
+/* Replace the coefficients in place.  Pointers are device memory when on_device != 0,
+ * else host; NULL keeps the current value.  Enqueued on stream (graph-safe when on_device). */
+int mtp_set_params(mtp_model* m, const double* radial, const double* linear, const double* shift,
+                   int on_device, void* stream);
+
+/* Build the canonical neighbour list of a system into caller buffers (device).
+ * off must hold N + 1 ints; j, shift and rev must hold cap ints each (rev may be NULL).
+ * *n_pairs (host) receives the pair count.  If it exceeds cap, nothing but off is written
+ * and MTP_ERR_CAPACITY is returned.  Synchronizes the stream once (to read the count). */
+int mtp_neighbors(mtp_model* m, const mtp_system* sys, int* off, int* j, int* shift, int* rev,
+                  long long cap, long long* n_pairs, void* stream);
+
+/* Energy, forces and virial (device outputs; any may be NULL):
+ *   energy [1], e_atom [N], forces [N][3], virial [6] as xx, yy, zz, xy, xz, yz with
+ *   W_ab = -sum_pairs d_a g_b (g = dE_i/dd_ij), positive under repulsion.
+ * nl: a list from mtp_neighbors for these positions, or NULL to build one internally
+ * (then the call synchronizes once).  Results are deterministic run to run. */
+int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double* energy,
+                double* e_atom, double* forces, double* virial, void* stream);
+
+/* Neighbourhood-mode extrapolation grade (Section 2.3 of the paper):
+ *   grade [N] (device) = max_k |(B_i Ainv)_k|, grade_max [1] (device) = max_i grade_i.
+ * ainv: device [n_alpha][n_alpha] row-major.  mode: MTP_GRADE_FP64 or MTP_GRADE_FP32SPLIT.
+ * When grade_select or grade_break is set in the parameters the call synchronizes, compares
+ * grade_max and returns MTP_GRADE_SELECT / MTP_GRADE_BREAK (outputs written either way). */
+int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
+              int mode, double* grade, double* grade_max, void* stream);
+
+/* Vector-Jacobian product of (E, F) with respect to the coefficients:
+ *   d_linear [n_alpha], d_radial [n_species^2 n_mu n_cheb], d_shift [n_species] (device) =
+ *   ebar dE/dtheta + sum_k fbar_k . dF_k/dtheta,  fbar device [N][3].
+ * For the loss (E - E0)^2 + sum |F - F0|^2 pass ebar = 2 (E - E0), fbar = 2 (F - F0). */
+int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double ebar,
+                   const double* fbar, double* d_linear, double* d_radial, double* d_shift,
+                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTP_H */

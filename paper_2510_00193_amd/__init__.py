@@ -1,0 +1,8 @@
+"""MI355X (gfx950) Moment Tensor Potential library: Python side of libmtp.so.
+
+The hot path (neighbour list, radial basis, moments, contractions, energy,
+adjoint to forces and virial, extrapolation grade, parameter gradients) runs
+in hand-written HIP kernels behind the C ABI declared in include/mtp.h.
+This package only builds the library and marshals arguments to it.
+"""
+from .api import NeighborList, Potential, compiled_levels  # noqa: F401

@@ -1,0 +1,182 @@
+"""PyTorch-facing wrapper of libmtp.so.
+
+PyTorch supplies device memory and the stream; every computation runs in the
+library's HIP kernels.  Tensors passed in must already live on the GPU with
+the documented dtypes (float64 positions, int32 species); nothing is
+converted or computed on the host here besides argument packing.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MtpNlist, MtpParams, MtpSystem, check
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape=None, name=""):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+@dataclass
+class NeighborList:
+    """Canonical CSR list (device int32 tensors)."""
+
+    off: torch.Tensor
+    j: torch.Tensor
+    shift: torch.Tensor
+    rev: torch.Tensor
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.j.shape[0])
+
+    def _c(self):
+        return MtpNlist(self.off.data_ptr(), self.j.data_ptr() if self.n_pairs else None,
+                        self.shift.data_ptr() if self.n_pairs else None,
+                        self.rev.data_ptr() if self.n_pairs else None, self.n_pairs)
+
+
+def compiled_levels():
+    lib = _lib.load()
+    n = ctypes.c_int()
+    buf = (ctypes.c_int * 64)()
+    check(lib.mtp_levels(ctypes.byref(n), buf))
+    return [buf[k] for k in range(n.value)]
+
+
+class Potential:
+    """One MTP model on the current GPU."""
+
+    def __init__(self, level, n_species, n_cheb, r_min, r_cut, radial, linear, shift, precision="fp64",
+                 chunk_atoms=0, grade_select=0.0, grade_break=0.0):
+        self._lib = _lib.load()
+        self._h = None
+        radial = np.ascontiguousarray(radial, dtype=np.float64)
+        linear = np.ascontiguousarray(linear, dtype=np.float64)
+        shift = np.ascontiguousarray(shift, dtype=np.float64)
+        prec = {"fp64": _lib.MTP_FP64, "fp32": _lib.MTP_FP32_MOMENTS}[precision]
+        p = MtpParams(int(level), int(n_species), int(n_cheb), float(r_min), float(r_cut),
+                      radial.ctypes.data_as(_lib.c_double_p), linear.ctypes.data_as(_lib.c_double_p),
+                      shift.ctypes.data_as(_lib.c_double_p), prec, int(chunk_atoms), float(grade_select),
+                      float(grade_break))
+        h = ctypes.c_void_p()
+        check(self._lib.mtp_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.level, self.n_species, self.n_cheb = int(level), int(n_species), int(n_cheb)
+        self.r_min, self.r_cut = float(r_min), float(r_cut)
+        a, mu, nm, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(self._lib.mtp_sizes(h, ctypes.byref(a), ctypes.byref(mu), ctypes.byref(nm), ctypes.byref(nc)))
+        self.n_alpha, self.n_mu, self.n_moments, self.n_components = a.value, mu.value, nm.value, nc.value
+
+    @classmethod
+    def from_params(cls, p, **kw):
+        return cls(p.level, p.n_species, p.n_cheb, p.r_min, p.r_cut, p.radial, p.linear, p.shift, **kw)
+
+    def close(self):
+        if self._h is not None:
+            self._lib.mtp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ helpers
+    def _system(self, pos, species, cell):
+        n = int(pos.shape[0])
+        _dev(pos, torch.float64, (n, 3), "pos")
+        _dev(species, torch.int32, (n,), "species")
+        cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(9)
+        s = MtpSystem(n, pos.data_ptr() if n else None, species.data_ptr() if n else None,
+                      (ctypes.c_double * 9)(*cell.tolist()))
+        return s, n
+
+    def set_params(self, radial=None, linear=None, shift=None):
+        """Replace coefficients in place (device tensors, float64)."""
+        args = []
+        for t in (radial, linear, shift):
+            args.append(_ptr(_dev(t, torch.float64, name="coefficients")) if t is not None else None)
+        check(self._lib.mtp_set_params(self._h, *args, 1, _stream()))
+
+    def neighbors(self, pos, species, cell, cap=None):
+        sysc, n = self._system(pos, species, cell)
+        dev = pos.device
+        off = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        total = ctypes.c_longlong()
+        if cap is None:
+            check(self._lib.mtp_neighbors(self._h, ctypes.byref(sysc), _ptr(off), None, None, None, 0,
+                                          ctypes.byref(total), _stream()), (_lib.MTP_OK, _lib.MTP_ERR_CAPACITY))
+            cap = total.value
+        j = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        sh = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        rev = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        check(self._lib.mtp_neighbors(self._h, ctypes.byref(sysc), _ptr(off), _ptr(j), _ptr(sh), _ptr(rev),
+                                      int(cap), ctypes.byref(total), _stream()))
+        p = total.value
+        return NeighborList(off, j[:p], sh[:p], rev[:p])
+
+    def compute(self, pos, species, cell, nlist=None, forces=True, virial=True, e_atom=False):
+        sysc, n = self._system(pos, species, cell)
+        dev = pos.device
+        e = torch.empty(1, dtype=torch.float64, device=dev)
+        ea = torch.empty(n, dtype=torch.float64, device=dev) if e_atom else None
+        f = torch.empty((n, 3), dtype=torch.float64, device=dev) if forces else None
+        w = torch.empty(6, dtype=torch.float64, device=dev) if virial else None
+        nl = ctypes.byref(nlist._c()) if nlist is not None else None
+        check(self._lib.mtp_compute(self._h, ctypes.byref(sysc), nl, _ptr(e), _ptr(ea), _ptr(f), _ptr(w),
+                                    _stream()))
+        out = {"energy": e[0]}
+        if forces:
+            out["forces"] = f
+        if virial:
+            out["virial"] = w
+        if e_atom:
+            out["e_atom"] = ea
+        return out
+
+    def grade(self, pos, species, cell, ainv, nlist=None, mode="fp64"):
+        sysc, n = self._system(pos, species, cell)
+        dev = pos.device
+        _dev(ainv, torch.float64, (self.n_alpha, self.n_alpha), "ainv")
+        g = torch.empty(n, dtype=torch.float64, device=dev)
+        gm = torch.empty(1, dtype=torch.float64, device=dev)
+        md = {"fp64": _lib.MTP_GRADE_FP64, "fp32split": _lib.MTP_GRADE_FP32SPLIT}[mode]
+        nl = ctypes.byref(nlist._c()) if nlist is not None else None
+        code = check(self._lib.mtp_grade(self._h, ctypes.byref(sysc), nl, _ptr(ainv), md, _ptr(g), _ptr(gm),
+                                         _stream()),
+                     (_lib.MTP_OK, _lib.MTP_GRADE_SELECT, _lib.MTP_GRADE_BREAK))
+        return {"grade": g, "grade_max": gm[0], "status": code}
+
+    def param_grad(self, pos, species, cell, ebar, fbar, nlist=None):
+        sysc, n = self._system(pos, species, cell)
+        dev = pos.device
+        _dev(fbar, torch.float64, (n, 3), "fbar")
+        dl = torch.empty(self.n_alpha, dtype=torch.float64, device=dev)
+        dr = torch.empty((self.n_species, self.n_species, self.n_mu, self.n_cheb), dtype=torch.float64, device=dev)
+        ds = torch.empty(self.n_species, dtype=torch.float64, device=dev)
+        nl = ctypes.byref(nlist._c()) if nlist is not None else None
+        check(self._lib.mtp_param_grad(self._h, ctypes.byref(sysc), nl, float(ebar), _ptr(fbar), _ptr(dl),
+                                       _ptr(dr), _ptr(ds), _stream()))
+        return dl, dr, ds

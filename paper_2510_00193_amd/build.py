@@ -1,0 +1,122 @@
+"""Build libmtp.so for gfx950: generate the per-level programs, compile with hipcc, link.
+
+Usage: python -m paper_2510_00193_amd.build [--levels 10,16] [--jobs 8]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+GEN = os.path.join(CSRC, "gen")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libmtp.so")
+INCLUDE = os.path.join(ROOT, "include")
+
+# level -> number of moment-entry groups (register budget of the lane-per-atom kernels)
+LEVELS = {2: 1, 4: 1, 6: 1, 8: 1, 10: 1, 12: 1, 14: 1, 16: 1, 18: 2, 20: 3}
+DEFAULT_LEVELS = (2, 4, 6, 8, 10, 12, 14, 16, 20)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=on",
+    # no packed fp32 instructions anywhere in this library
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path):
+        with open(path) as fh:
+            if fh.read() == text:
+                return
+    with open(path, "w") as fh:
+        fh.write(text)
+
+
+def generate(levels):
+    from .codegen.emit import write_level
+    os.makedirs(GEN, exist_ok=True)
+    for lv in levels:
+        write_level(lv, GEN, LEVELS[lv])
+        _write_if_changed(os.path.join(GEN, f"mtp_L{lv}.hip"),
+                          f'// Generated: kernels of level {lv}.\n#include <hip/hip_runtime.h>\n#include "gen/mtp_L{lv}.inc"\n'
+                          f'#include "mtp_level_impl.h"\nMTP_DEFINE_LEVEL(Lv{lv}, {lv})\n')
+    _write_if_changed(os.path.join(GEN, "levels.inc"),
+                      "".join(f"MTP_LEVEL({lv})\n" for lv in levels))
+
+
+def _compile(src, obj):
+    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    t0 = time.time()
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    return obj, time.time() - t0
+
+
+def sources(levels):
+    out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_nbr.hip", "mtp_common.hip")]
+    out += [os.path.join(GEN, f"mtp_L{lv}.hip") for lv in levels]
+    return out
+
+
+def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True):
+    levels = tuple(sorted(levels))
+    generate(levels)
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources(levels)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = {}
+        for src in srcs:
+            obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+            lang = ["-x", "hip"] if src.endswith(".cpp") else []
+            futs[ex.submit(_compile_lang, src, obj, lang)] = src
+        for fut in cf.as_completed(futs):
+            obj, dt = fut.result()
+            objs.append(obj)
+            if verbose:
+                print(f"  compiled {os.path.basename(futs[fut])} in {dt:.1f}s", flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *sorted(objs)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    shutil.move(tmp, LIB)
+    if verbose:
+        print(f"  linked {LIB}", flush=True)
+    return LIB
+
+
+def _compile_lang(src, obj, lang):
+    cmd = [HIPCC, *FLAGS, *lang, "-c", src, "-o", obj]
+    t0 = time.time()
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout[-4000:]}\n{res.stderr[-8000:]}")
+    return obj, time.time() - t0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--levels", default=",".join(str(l) for l in DEFAULT_LEVELS))
+    ap.add_argument("--jobs", type=int, default=None)
+    args = ap.parse_args(argv)
+    levels = [int(x) for x in args.levels.split(",") if x]
+    build(levels, args.jobs)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

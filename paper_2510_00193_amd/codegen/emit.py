@@ -1,0 +1,417 @@
+"""Emit the per-level device code of the MTP evaluation as a HIP header.
+
+For one level the header defines a traits struct ``Lv<L>`` with static
+device functions, all straight-line code with compile-time indices so that
+per-atom state stays in registers:
+
+  acc_moments<G>(m, f, x, y, z)        m[e] += f[mu_e] x^a y^b z^c   (entry group G)
+  pair_grad<G>(mb, f, fp, x, y, z, ...) gradient of sum_e mb[e] f_mu x^a y^b z^c w.r.t. d
+  fwd(M, C)                             connected contractions C_q from moments
+  products(C, xi, Cb, B)                basis values, site energy, adjoints of C_q
+  rev<G>(M, Cb, mb)                     mb[e] += sum_q Cb_q dC_q/dm_e   (entries of group G)
+  tan(M, Md, C, Cd)                     forward-mode tangent of the contractions
+  ...
+
+The host-side tables (moment layout, product trie, basis order) are
+emitted too, for argument checking and tests.
+"""
+from __future__ import annotations
+
+import os
+from collections import defaultdict
+from fractions import Fraction
+
+from .program import Program, build_program
+
+
+def _lit(w) -> str:
+    v = float(w)
+    if v == int(v) and abs(v) < 1e15:
+        return f"R({int(v)})"
+    return f"R({v!r})"
+
+
+class _W:
+    def __init__(self):
+        self.lines = []
+        self.ind = 0
+
+    def __call__(self, s=""):
+        self.lines.append("  " * self.ind + s)
+
+    def push(self):
+        self.ind += 1
+
+    def pop(self):
+        self.ind -= 1
+
+    def text(self):
+        return "\n".join(self.lines) + "\n"
+
+
+def entry_groups(prog: Program, n_groups: int):
+    """Split the flat moment layout into n_groups contiguous ranges of similar size."""
+    n = prog.n_mom
+    bounds = [round(k * n / n_groups) for k in range(n_groups + 1)]
+    return [(bounds[k], bounds[k + 1]) for k in range(n_groups)]
+
+
+def _ref(r, mvar="me"):
+    kind, k = r
+    if kind == "m":
+        return f"{mvar}{k}"
+    if kind == "t":
+        return f"t{k}"
+    return f"C[{k}]"
+
+
+def _emit_pair_functions(w: _W, prog: Program, groups):
+    items = prog.layout.items
+    maxnu = prog.max_nu
+    nmu = prog.n_mu
+    for gi, (lo, hi) in enumerate(groups):
+        ents = list(range(lo, hi))
+        gnu = max(a + b + c for (_, a, b, c) in (items[e] for e in ents))
+        # ---------------- moment accumulation
+        w(f"// entries [{lo}, {hi}) of the moment layout")
+        w("template <class R>")
+        w(f"static __device__ __forceinline__ void acc_moments_g{gi}(R* __restrict__ m, const R* __restrict__ f, R x, R y, R z) {{")
+        w.push()
+        _emit_powers(w, gnu)
+        by_mono = defaultdict(list)
+        for e in ents:
+            mu, a, b, c = items[e]
+            by_mono[(a, b, c)].append((e, mu))
+        _emit_monomials(w, sorted(by_mono, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])), "mono")
+        for abc in sorted(by_mono, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])):
+            for e, mu in by_mono[abc]:
+                w(f"m[{e - lo}] = fma(f[{mu}], {_mono_name(abc)}, m[{e - lo}]);")
+        w.pop()
+        w("}")
+        # ---------------- gradient of the moment contraction with mb
+        w("template <class R>")
+        w(f"static __device__ __forceinline__ void pair_grad_g{gi}(const R* __restrict__ mb, const R* __restrict__ f,")
+        w("    const R* __restrict__ fp, R x, R y, R z, R& gx, R& gy, R& gz, R& u) {")
+        w.push()
+        _emit_powers(w, gnu)
+        need = set()
+        for e in ents:
+            mu, a, b, c = items[e]
+            need.add((a, b, c))
+            if a:
+                need.add((a - 1, b, c))
+            if b:
+                need.add((a, b - 1, c))
+            if c:
+                need.add((a, b, c - 1))
+        order = sorted(need, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1]))
+        _emit_monomials(w, order, "mono")
+        mus = sorted({items[e][0] for e in ents})
+        for mu in mus:
+            w(f"R s{mu} = R(0);")
+        by_mono = defaultdict(list)
+        for e in ents:
+            mu, a, b, c = items[e]
+            by_mono[(a, b, c)].append((e, mu))
+        for abc in sorted(by_mono, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])):
+            lst = by_mono[abc]
+            for e, mu in lst:
+                w(f"s{mu} = fma(mb[{e - lo}], {_mono_name(abc)}, s{mu});")
+            a, b, c = abc
+            if a + b + c == 0:
+                continue
+            # t = sum_mu f_mu mb[mu, abc]
+            first = True
+            for e, mu in lst:
+                if first:
+                    w(f"{{ R t = f[{mu}] * mb[{e - lo}];")
+                    first = False
+                else:
+                    w(f"  t = fma(f[{mu}], mb[{e - lo}], t);")
+            for var, k, low in (("gx", a, (a - 1, b, c)), ("gy", b, (a, b - 1, c)), ("gz", c, (a, b, c - 1))):
+                if k == 0:
+                    continue
+                if k == 1:
+                    w(f"  {var} = fma(t, {_mono_name(low)}, {var});")
+                else:
+                    w(f"  {var} = fma(R({k}) * t, {_mono_name(low)}, {var});")
+            w("}")
+        for mu in mus:
+            w(f"u = fma(fp[{mu}], s{mu}, u);")
+        w.pop()
+        w("}")
+
+
+def _mono_name(abc):
+    a, b, c = abc
+    return f"mono_{a}_{b}_{c}"
+
+
+def _emit_powers(w, nu):
+    for v in "xyz":
+        for k in range(2, nu + 1):
+            prev = v if k == 2 else f"{v}{k - 1}"
+            w(f"const R {v}{k} = {prev} * {v};")
+
+
+def _pw(v, k):
+    if k == 0:
+        return None
+    if k == 1:
+        return v
+    return f"{v}{k}"
+
+
+def _emit_monomials(w, order, _prefix):
+    have = set()
+    for abc in order:
+        a, b, c = abc
+        name = _mono_name(abc)
+        if a + b + c == 0:
+            w(f"const R {name} = R(1);")
+            have.add(abc)
+            continue
+        # reuse a lower monomial times one power when possible
+        done = False
+        for (da, db, dc), var in (((0, 0, 1), "z"), ((0, 1, 0), "y"), ((1, 0, 0), "x")):
+            low = (a - da, b - db, c - dc)
+            if min(low) >= 0 and low in have:
+                w(f"const R {name} = {_mono_name(low)} * {var};")
+                done = True
+                break
+        if not done:
+            parts = [p for p in (_pw("x", a), _pw("y", b), _pw("z", c)) if p]
+            w(f"const R {name} = {' * '.join(parts)};")
+        have.add(abc)
+
+
+def _group_ops(ops):
+    """Group a block's ops by (dst, x): {(dst, x): [(y, w), ...]} preserving first-seen order."""
+    groups = {}
+    for dst, x, y, wgt in ops:
+        groups.setdefault((dst, x), []).append((y, wgt))
+    return groups
+
+
+def _emit_block_forward(w: _W, blk, with_output=True):
+    for k in range(blk.n_temp):
+        w(f"R t{k} = R(0);")
+    for (dst, x), lst in _group_ops(blk.ops).items():
+        if dst[0] == "c" and not with_output:
+            continue
+        if lst[0][0] is None:
+            w(f"{_ref(dst)} = {_ref(x)};")
+            continue
+        _emit_inner(w, lst, "s")
+        w(f"{_ref(dst)} = fma({_ref(x)}, s, {_ref(dst)}); }}")
+
+
+def _emit_inner(w, lst, var):
+    (y0, w0) = lst[0]
+    if w0 == 1:
+        w(f"{{ R {var} = {_ref(y0)};")
+    else:
+        w(f"{{ R {var} = {_lit(w0)} * {_ref(y0)};")
+    for y, wgt in lst[1:]:
+        if wgt == 1:
+            w(f"  {var} += {_ref(y)};")
+        else:
+            w(f"  {var} = fma({_lit(wgt)}, {_ref(y)}, {var});")
+
+
+def _emit_components_forward(w: _W, prog: Program):
+    w("template <class R, class MA>")
+    w("static __device__ __forceinline__ void fwd(const MA& M, R* __restrict__ C) {")
+    w.push()
+    for blk in prog.blocks:
+        w(f"{{  // contraction {blk.q}")
+        w.push()
+        for e in blk.entries:
+            w(f"const R me{e} = M({e});")
+        w(f"C[{blk.q}] = R(0);")
+        _emit_block_forward(w, blk)
+        w.pop()
+        w("}")
+    w.pop()
+    w("}")
+
+
+def _emit_components_reverse(w: _W, prog: Program, groups):
+    for gi, (lo, hi) in enumerate(groups):
+        w("template <class R, class MA>")
+        w(f"static __device__ __forceinline__ void rev_g{gi}(const MA& M, const R* __restrict__ Cb, R* __restrict__ mb) {{")
+        w.push()
+        for blk in prog.blocks:
+            if not any(lo <= e < hi for e in blk.entries):
+                continue
+            w(f"{{  // contraction {blk.q}")
+            w.push()
+            for e in blk.entries:
+                w(f"const R me{e} = M({e});")
+            w(f"const R cb = Cb[{blk.q}];")
+            _emit_block_forward(w, blk, with_output=False)
+            for k in range(blk.n_temp):
+                w(f"R tb{k} = R(0);")
+            _emit_block_reverse(w, blk, lo, hi)
+            w.pop()
+            w("}")
+        w.pop()
+        w("}")
+
+
+def _adj(ref, lo, hi):
+    kind, k = ref
+    if kind == "t":
+        return f"tb{k}"
+    if kind == "m":
+        return f"mb[{k - lo}]" if lo <= k < hi else None
+    return "cb"
+
+
+def _emit_block_reverse(w: _W, blk, lo, hi):
+    # walk steps backwards: ops were appended step by step
+    rev_ops = list(reversed(blk.ops))
+    # group by (dst, x) for x-adjoints and by (dst, y) for y-adjoints, in reverse step order
+    seen_dst = []
+    by_dst = defaultdict(list)
+    for dst, x, y, wgt in rev_ops:
+        if dst not in by_dst:
+            seen_dst.append(dst)
+        by_dst[dst].append((x, y, wgt))
+    for dst in seen_dst:
+        lst = by_dst[dst]
+        db = _adj(dst, lo, hi)
+        if lst[0][1] is None:
+            (x, _, _), = lst
+            tgt = _adj(x, lo, hi)
+            if tgt:
+                w(f"{tgt} += {db};")
+            continue
+        xs = {}
+        ys = {}
+        for x, y, wgt in lst:
+            xs.setdefault(x, []).append((y, wgt))
+            ys.setdefault(y, []).append((x, wgt))
+        for x, l2 in xs.items():
+            tgt = _adj(x, lo, hi)
+            if not tgt:
+                continue
+            _emit_inner(w, l2, "s")
+            w(f"{tgt} = fma({db}, s, {tgt}); }}")
+        for y, l2 in ys.items():
+            tgt = _adj(y, lo, hi)
+            if not tgt:
+                continue
+            _emit_inner(w, l2, "s")
+            w(f"{tgt} = fma({db}, s, {tgt}); }}")
+
+
+def _emit_products(w: _W, prog: Program):
+    children = defaultdict(list)
+    roots = []
+    for a, (parent, comp) in enumerate(prog.trie):
+        if parent < 0:
+            roots.append(a)
+        else:
+            children[parent].append(a)
+    w("// E_i contribution sum_alpha xi_alpha B_alpha; Cb_q = dE_i/dC_q; B written when Bo != nullptr")
+    w("template <class R>")
+    w("static __device__ __forceinline__ double products(const R* __restrict__ C, const double* __restrict__ xi,")
+    w("    R* __restrict__ Cb, double* __restrict__ Bo, long ldb) {")
+    w.push()
+    w("double e = 0.0;")
+    for q in range(prog.n_comp):
+        w(f"Cb[{q}] = R(0);")
+
+    def node2(a, parent_var):
+        # variant that leaves bb{a} declared in the enclosing scope
+        parent, comp = prog.trie[a]
+        w(f"R bb{a};")
+        w("{")
+        w.push()
+        if parent_var is None:
+            w(f"const R b = C[{comp}];")
+        else:
+            w(f"const R b = {parent_var} * C[{comp}];")
+        w(f"e = fma(xi[{a}], double(b), e);")
+        w(f"if (Bo) Bo[{a} * ldb] = double(b);")
+        w(f"bb{a} = R(xi[{a}]);")
+        if children[a]:
+            w(f"const R p{a} = b;")
+            for ch in children[a]:
+                node2(ch, f"p{a}")
+                _, ccomp = prog.trie[ch]
+                w(f"bb{a} = fma(bb{ch}, C[{ccomp}], bb{a});")
+        w.pop()
+        w("}")
+        if parent_var is None:
+            w(f"Cb[{comp}] += bb{a};")
+        else:
+            w(f"Cb[{comp}] = fma(bb{a}, {parent_var}, Cb[{comp}]);")
+
+    for a in roots:
+        node2(a, None)
+    w("return e;")
+    w.pop()
+    w("}")
+
+
+def _emit_dispatchers(w: _W, n_groups: int):
+    sigs = (
+        ("acc_moments", "R* __restrict__ m, const R* __restrict__ f, R x, R y, R z", "m, f, x, y, z", "class R"),
+        ("pair_grad", "const R* __restrict__ mb, const R* __restrict__ f, const R* __restrict__ fp, R x, R y, R z, "
+                      "R& gx, R& gy, R& gz, R& u", "mb, f, fp, x, y, z, gx, gy, gz, u", "class R"),
+        ("rev", "const MA& M, const R* __restrict__ Cb, R* __restrict__ mb", "M, Cb, mb", "class R, class MA"),
+    )
+    for name, params, args, tparams in sigs:
+        w(f"template <int G, {tparams}>")
+        w(f"static __device__ __forceinline__ void {name}({params}) {{")
+        w.push()
+        for g in range(n_groups):
+            kw = "if constexpr" if g == 0 else "else if constexpr"
+            targs = "<R>" if name != "rev" else "<R, MA>"
+            w(f"{kw} (G == {g}) {name}_g{g}{targs}({args});")
+        w.pop()
+        w("}")
+
+
+def emit_level(level: int, n_groups: int = 1) -> str:
+    prog = build_program(level)
+    groups = entry_groups(prog, n_groups)
+    w = _W()
+    w(f"// Generated MTP level-{level} program.  Do not edit; produced by codegen/emit.py.")
+    w("#pragma once")
+    w(f"struct Lv{level} {{")
+    w.push()
+    w(f"static constexpr int LEVEL = {level};")
+    w(f"static constexpr int NMOM = {prog.n_mom};")
+    w(f"static constexpr int NCOMP = {prog.n_comp};")
+    w(f"static constexpr int NALPHA = {prog.n_alpha};")
+    w(f"static constexpr int NMU = {prog.n_mu};")
+    w(f"static constexpr int MAXNU = {prog.max_nu};")
+    w(f"static constexpr int NGROUP = {len(groups)};")
+    w(f"static constexpr int TRIPLES = {prog.triple_count()};")
+    w("static constexpr int GROUP_LO[NGROUP] = {" + ", ".join(str(g[0]) for g in groups) + "};")
+    w("static constexpr int GROUP_HI[NGROUP] = {" + ", ".join(str(g[1]) for g in groups) + "};")
+    _emit_pair_functions(w, prog, groups)
+    _emit_components_forward(w, prog)
+    _emit_components_reverse(w, prog, groups)
+    _emit_products(w, prog)
+    _emit_dispatchers(w, len(groups))
+    w.pop()
+    w("};")
+    return w.text()
+
+
+def write_level(level: int, out_dir: str, n_groups: int = 1) -> str:
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, f"mtp_L{level}.inc")
+    text = emit_level(level, n_groups)
+    old = None
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = fh.read()
+    if old != text:
+        with open(path, "w") as fh:
+            fh.write(text)
+    return path

@@ -1,0 +1,327 @@
+// C ABI of the MTP library: argument checking, workspace, and the launch sequence of the
+// hot path (neighbour list -> moments -> contractions -> adjoint -> pair gradients ->
+// force gather and fixed-order sums).  All device work goes to the caller's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "mtp.h"
+#include "mtp_internal.h"
+#include "mtp_api_internal.h"
+
+namespace mtp {
+#define MTP_LEVEL(N) LevelOps level_ops_##N();
+#include "gen/levels.inc"
+#undef MTP_LEVEL
+
+static bool find_level(int level, LevelOps* out) {
+  switch (level) {
+#define MTP_LEVEL(N) \
+  case N:            \
+    *out = level_ops_##N(); \
+    return true;
+#include "gen/levels.inc"
+#undef MTP_LEVEL
+    default:
+      return false;
+  }
+}
+}  // namespace mtp
+
+using namespace mtp;
+
+static thread_local std::string g_err;
+
+int mtp_fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) return mtp_fail(MTP_ERR_HIP, std::string(#expr ": ") +   \
+                                                           hipGetErrorString(e_)); \
+  } while (0)
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+
+int DevBuf::reserve(size_t n) {
+  if (bytes >= n) return MTP_OK;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  if (n == 0) return MTP_OK;
+  if (hipMalloc(&p, n) != hipSuccess) {
+    (void)hipGetLastError();
+    return mtp_fail(MTP_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
+  }
+  bytes = n;
+  return MTP_OK;
+}
+
+extern "C" {
+
+const char* mtp_last_error(void) { return g_err.c_str(); }
+
+int mtp_levels(int* n, int* levels) {
+  if (!n) return mtp_fail(MTP_ERR_ARG, "n is NULL");
+  int k = 0;
+#define MTP_LEVEL(N) \
+  if (levels) levels[k] = N; \
+  ++k;
+#include "gen/levels.inc"
+#undef MTP_LEVEL
+  *n = k;
+  return MTP_OK;
+}
+
+int mtp_create(const mtp_params* p, mtp_model** out) {
+  if (!p || !out) return mtp_fail(MTP_ERR_ARG, "null argument");
+  *out = nullptr;
+  LevelOps ops;
+  if (!find_level(p->level, &ops))
+    return mtp_fail(MTP_ERR_LEVEL, "level " + std::to_string(p->level) + " is not compiled");
+  if (p->n_species < 1 || p->n_species > kMaxSpecies)
+    return mtp_fail(MTP_ERR_ARG, "n_species must be in [1, " + std::to_string(kMaxSpecies) + "]");
+  if (p->n_cheb < 1 || p->n_cheb > kMaxChebHost)
+    return mtp_fail(MTP_ERR_ARG, "n_cheb must be in [1, 16]");
+  if (!(p->r_min >= 0.0) || !(p->r_cut > p->r_min) || !isfinite(p->r_cut))
+    return mtp_fail(MTP_ERR_ARG, "need 0 <= r_min < r_cut");
+  if (!p->radial || !p->linear || !p->shift) return mtp_fail(MTP_ERR_ARG, "null coefficients");
+  if (p->precision != MTP_FP64 && p->precision != MTP_FP32_MOMENTS)
+    return mtp_fail(MTP_ERR_ARG, "unknown precision");
+  if (p->chunk_atoms < 0) return mtp_fail(MTP_ERR_ARG, "chunk_atoms < 0");
+  const long nrad = (long)p->n_species * p->n_species * ops.nmu * p->n_cheb;
+  if (nrad > kMaxRadial) return mtp_fail(MTP_ERR_ARG, "radial table too large");
+  mtp_model* m = new mtp_model();
+  m->ops = ops;
+  m->nsp = p->n_species;
+  m->ncheb = p->n_cheb;
+  m->rmin = p->r_min;
+  m->rcut = p->r_cut;
+  m->precision = p->precision;
+  m->chunk = p->chunk_atoms > 0 ? p->chunk_atoms : kDefaultChunk;
+  m->grade_select = p->grade_select;
+  m->grade_break = p->grade_break;
+  m->nrad = nrad;
+  int rc = MTP_OK;
+  if ((rc = m->radial.reserve(nrad * sizeof(double))) || (rc = m->linear.reserve(ops.nalpha * sizeof(double))) ||
+      (rc = m->shift.reserve(m->nsp * sizeof(double)))) {
+    delete m;
+    return rc;
+  }
+  if (hipMemcpy(m->radial.p, p->radial, nrad * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->linear.p, p->linear, ops.nalpha * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->shift.p, p->shift, m->nsp * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    delete m;
+    return mtp_fail(MTP_ERR_HIP, "copying coefficients failed");
+  }
+  m->nbr = nbr_work_create();
+  *out = m;
+  return MTP_OK;
+}
+
+void mtp_destroy(mtp_model* m) {
+  if (!m) return;
+  nbr_work_destroy(m->nbr);
+  delete m;
+}
+
+int mtp_sizes(const mtp_model* m, int* n_alpha, int* n_mu, int* n_moments, int* n_components) {
+  if (!m) return mtp_fail(MTP_ERR_ARG, "null model");
+  if (n_alpha) *n_alpha = m->ops.nalpha;
+  if (n_mu) *n_mu = m->ops.nmu;
+  if (n_moments) *n_moments = m->ops.nmom;
+  if (n_components) *n_components = m->ops.ncomp;
+  return MTP_OK;
+}
+
+int mtp_set_params(mtp_model* m, const double* radial, const double* linear, const double* shift,
+                   int on_device, void* stream) {
+  if (!m) return mtp_fail(MTP_ERR_ARG, "null model");
+  hipStream_t s = (hipStream_t)stream;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (radial) HIP_TRY(hipMemcpyAsync(m->radial.p, radial, m->nrad * sizeof(double), kind, s));
+  if (linear) HIP_TRY(hipMemcpyAsync(m->linear.p, linear, m->ops.nalpha * sizeof(double), kind, s));
+  if (shift) HIP_TRY(hipMemcpyAsync(m->shift.p, shift, m->nsp * sizeof(double), kind, s));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(s));
+  return MTP_OK;
+}
+
+}  // extern "C"
+
+static int check_system(const mtp_model* m, const mtp_system* sys) {
+  if (!m || !sys) return mtp_fail(MTP_ERR_ARG, "null model or system");
+  if (sys->n_atoms < 0) return mtp_fail(MTP_ERR_ARG, "n_atoms < 0");
+  if (sys->n_atoms > 0 && (!sys->pos || !sys->species))
+    return mtp_fail(MTP_ERR_ARG, "null positions or species");
+  for (int k = 0; k < 9; ++k)
+    if (!isfinite(sys->cell[k])) return mtp_fail(MTP_ERR_CELL, "non-finite cell");
+  return MTP_OK;
+}
+
+// Build the canonical list into the given buffers (or the model's own when off is NULL).
+int build_neighbors(mtp_model* m, const mtp_system* sys, int* off, int* nj, int* shift, int* rev,
+                    long long cap, long long* n_pairs, bool own, hipStream_t s) {
+  NbrPlan plan;
+  int st = 0;
+  nbr_plan(sys->cell, m->rcut, &plan, &st);
+  if (st) return mtp_fail(MTP_ERR_CELL, "singular cell");
+  const int n = sys->n_atoms;
+  int rc;
+  if (own) {
+    if ((rc = m->nl_off.reserve((n + 1) * sizeof(int)))) return rc;
+    off = (int*)m->nl_off.p;
+  }
+  if (!plan.cells && n > kMaxAllPairsAtoms)
+    return mtp_fail(MTP_ERR_CELL, "cell thinner than r_cut for a system too large for the all-pairs search");
+  long long total = 0;
+  int flags[4] = {0, 0, 0, 0};
+  rc = nbr_count(plan, sys->pos, sys->species, m->nsp, n, sys->cell, m->rcut, m->nbr, off, &total,
+                 flags, s);
+  if (rc) return mtp_fail(rc, "neighbour count failed");
+  if (flags[0]) return mtp_fail(MTP_ERR_NONFINITE, "non-finite position");
+  if (flags[1]) return mtp_fail(MTP_ERR_ARG, "species outside [0, n_species)");
+  if (flags[2]) return mtp_fail(MTP_ERR_CELL, "an image shift does not fit in int8");
+  if (total >= (1LL << 31)) return mtp_fail(MTP_ERR_CAPACITY, "more than 2^31 - 1 pairs");
+  *n_pairs = total;
+  if (own) {
+    if ((rc = m->nl_j.reserve(total * sizeof(int))) || (rc = m->nl_shift.reserve(total * sizeof(int))) ||
+        (rc = m->nl_rev.reserve(total * sizeof(int))))
+      return rc;
+    nj = (int*)m->nl_j.p;
+    shift = (int*)m->nl_shift.p;
+    rev = (int*)m->nl_rev.p;
+  } else if (total > cap) {
+    return mtp_fail(MTP_ERR_CAPACITY, "pair capacity " + std::to_string(cap) + " < " +
+                                          std::to_string(total));
+  }
+  rc = nbr_fill(plan, sys->pos, n, sys->cell, m->rcut, m->nbr, off, nj, shift, rev, total, s);
+  if (rc) return mtp_fail(rc, "neighbour fill failed");
+  return MTP_OK;
+}
+
+extern "C" int mtp_neighbors(mtp_model* m, const mtp_system* sys, int* off, int* j, int* shift,
+                             int* rev, long long cap, long long* n_pairs, void* stream) {
+  int rc = check_system(m, sys);
+  if (rc) return rc;
+  if (!off || !n_pairs || (cap > 0 && (!j || !shift)) || cap < 0)
+    return mtp_fail(MTP_ERR_ARG, "null output buffer or negative capacity");
+  return build_neighbors(m, sys, off, j, shift, rev, cap, n_pairs, false, (hipStream_t)stream);
+}
+
+// Resolve the list to use: the caller's, or a freshly built internal one.
+int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_nlist* out,
+                  hipStream_t s) {
+  if (nl) {
+    if (!nl->off || (nl->n_pairs > 0 && (!nl->j || !nl->shift || !nl->rev)) || nl->n_pairs < 0)
+      return mtp_fail(MTP_ERR_ARG, "incomplete neighbour list");
+    *out = *nl;
+    return MTP_OK;
+  }
+  long long total = 0;
+  int rc = build_neighbors(m, sys, nullptr, nullptr, nullptr, nullptr, 0, &total, true, s);
+  if (rc) return rc;
+  out->off = (const int*)m->nl_off.p;
+  out->j = (const int*)m->nl_j.p;
+  out->shift = (const int*)m->nl_shift.p;
+  out->rev = (const int*)m->nl_rev.p;
+  out->n_pairs = total;
+  return MTP_OK;
+}
+
+SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist& nl) {
+  SysArgs a;
+  a.pos = sys->pos;
+  a.species = sys->species;
+  a.off = nl.off;
+  a.nj = nl.j;
+  a.shift = nl.shift;
+  a.radial = (const double*)m->radial.p;
+  for (int k = 0; k < 9; ++k) a.H[k] = sys->cell[k];
+  a.sa = 2.0 / (m->rcut - m->rmin);
+  a.sb = -(m->rmin + m->rcut) / (m->rcut - m->rmin);
+  a.rcut = m->rcut;
+  a.nsp = m->nsp;
+  a.nmu = m->ops.nmu;
+  a.ncheb = m->ncheb;
+  return a;
+}
+
+// Forward (moments, contractions, energies) and optionally the adjoint chain down to the
+// per-pair gradients g and per-workgroup virial partials, chunk by chunk.
+int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,
+                     bool backward, double* bvals, hipStream_t s) {
+  const LevelOps& L = m->ops;
+  const int n = sys->n_atoms;
+  const int chunk = std::max(1, std::min(m->chunk, std::max(n, 1)));
+  const long ld = chunk;
+  int rc;
+  if ((rc = m->mom.reserve((size_t)L.nmom * ld * sizeof(double))) ||
+      (rc = m->cbar.reserve((size_t)L.ncomp * ld * sizeof(double))))
+    return rc;
+  if (backward) {
+    const long nblocks = ((long)n + kLaneBlockHost - 1) / kLaneBlockHost + (n / chunk + 1);
+    if ((rc = m->mbar.reserve((size_t)L.nmom * ld * sizeof(double))) ||
+        (rc = m->g.reserve((size_t)std::max<long long>(nl.n_pairs, 1) * 3 * sizeof(double))) ||
+        (rc = m->wpart.reserve((size_t)nblocks * 6 * sizeof(double))))
+      return rc;
+  }
+  SysArgs a = make_sys_args(m, sys, nl);
+  double* mom = (double*)m->mom.p;
+  double* cbar = (double*)m->cbar.p;
+  double* mbar = (double*)m->mbar.p;
+  long blk = 0;
+  for (int i0 = 0; i0 < n; i0 += chunk) {
+    const int cn = std::min(chunk, n - i0);
+    for (int g = 0; g < L.ngroup; ++g) L.moments(g, a, i0, cn, mom, ld, s);
+    L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
+               (const double*)m->shift.p, m->nsp, e_atom, cbar, bvals, s);
+    if (backward) {
+      for (int g = 0; g < L.ngroup; ++g) L.prog_rev(g, mom, ld, cn, cbar, mbar, s);
+      for (int g = 0; g < L.ngroup; ++g)
+        L.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, s);
+      blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
+    }
+  }
+  m->wblocks = blk;
+  HIP_TRY(hipGetLastError());
+  return MTP_OK;
+}
+
+extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl,
+                           double* energy, double* e_atom, double* forces, double* virial,
+                           void* stream) {
+  int rc = check_system(m, sys);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int n = sys->n_atoms;
+  mtp_nlist use;
+  if ((rc = resolve_nlist(m, sys, nl, &use, s))) return rc;
+  double* ea = e_atom;
+  if (!ea) {
+    if ((rc = m->eatom.reserve((size_t)std::max(n, 1) * sizeof(double)))) return rc;
+    ea = (double*)m->eatom.p;
+  }
+  const bool backward = forces || virial;
+  if (n > 0) {
+    if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s))) return rc;
+  }
+  if (energy) launch_sum(ea, n, 1, energy, s);
+  if (forces && n > 0) launch_gather_forces(use.off, use.rev, (const double*)m->g.p, n, use.n_pairs, forces, s);
+  if (virial) {
+    if (n > 0)
+      launch_sum_virial((const double*)m->wpart.p, m->wblocks, virial, s);
+    else
+      HIP_TRY(hipMemsetAsync(virial, 0, 6 * sizeof(double), s));
+  }
+  HIP_TRY(hipGetLastError());
+  return MTP_OK;
+}

@@ -1,0 +1,43 @@
+// Host-side model and workspace shared by the library's API translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "mtp.h"
+#include "mtp_internal.h"
+
+constexpr int kDefaultChunk = 131072;  // atoms per chunk: bounds the per-atom workspace
+constexpr int kLaneBlockHost = 64;     // workgroup size of the lane-per-atom kernels
+constexpr int kMaxAllPairsAtoms = 200000;  // largest system searched pair by pair (thin cells)
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  int reserve(size_t n);
+};
+
+struct mtp_model {
+  mtp::LevelOps ops;
+  int nsp = 0, ncheb = 0, precision = 0, chunk = 0;
+  long nrad = 0;
+  double rmin = 0, rcut = 0, grade_select = 0, grade_break = 0;
+  DevBuf radial, linear, shift;                        // coefficients (device)
+  DevBuf nl_off, nl_j, nl_shift, nl_rev;               // internally built neighbour list
+  DevBuf mom, cbar, mbar, bvals, g, eatom, wpart;      // per-chunk / per-pair workspace
+  DevBuf scratch;
+  long wblocks = 0;
+  mtp::NbrWork* nbr = nullptr;
+};
+
+int mtp_fail(int code, const std::string& msg);
+int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_nlist* out,
+                  hipStream_t s);
+mtp::SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist& nl);
+int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,
+                     bool backward, double* bvals, hipStream_t s);

@@ -1,0 +1,65 @@
+// Host/device declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mtp {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxMu = 8;
+constexpr int kMaxRadial = 1024;  // doubles of the staged c[z_i][z_j][mu][b] table
+constexpr int kMaxChebHost = 16;
+
+// Per-system arguments of the pair kernels (passed by value: lands in kernel-argument SGPRs).
+struct SysArgs {
+  const double* pos;      // [N][3]
+  const int* species;     // [N]
+  const int* off;         // [N+1]
+  const int* nj;          // [P]
+  const int* shift;       // [P] packed int8 x3
+  const double* radial;   // [nsp][nsp][nmu][ncheb]
+  double H[9];            // rows = lattice vectors
+  double sa, sb, rcut;    // u = sa r + sb
+  int nsp, nmu, ncheb;
+};
+
+// Launchers of one compiled level (filled in by the level's translation unit).
+struct LevelOps {
+  int level, nmom, ncomp, nalpha, nmu, maxnu, ngroup, triples;
+  void (*moments)(int g, const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s);
+  void (*prog_fwd)(const double* m, long ld, int i0, int n, const int* species, const double* xi,
+                   const double* shift, int nsp, double* e_atom, double* cbar, double* bout,
+                   hipStream_t s);
+  void (*prog_rev)(int g, const double* m, long ld, int n, const double* cb, double* mb,
+                   hipStream_t s);
+  void (*backward)(int grp, const SysArgs& a, int i0, int n, const double* mb, long ld, double* g,
+                   int acc, double* wpart, hipStream_t s);
+};
+
+// neighbour list (mtp_nbr.hip)
+struct NbrWork;
+struct NbrPlan {
+  bool cells;              // cell-list path (else all-pairs with per-pair image ranges)
+  int nb[3];               // bins per axis (cell path)
+  double Hinv[9];
+  double reach[3];         // r_cut |b_k|
+};
+void nbr_plan(const double* H, double rcut, NbrPlan* plan, int* status);
+// Counting pass: writes off[0..N] (exclusive scan of counts) and returns the pair total
+// through the host pointer (synchronizes).  Host flags[4]: [0] a non-finite position,
+// [1] a species outside [0, nsp), [2] an image index outside the packed int8 range.
+int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int nsp, int n,
+              const double* H, double rcut, NbrWork* w, int* off, long long* total, int* flags,
+              hipStream_t s);
+int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, double rcut,
+             NbrWork* w, const int* off, int* nj, int* shift, int* rev, long long total,
+             hipStream_t s);
+NbrWork* nbr_work_create();
+void nbr_work_destroy(NbrWork* w);
+
+// level-independent kernels (mtp_common.hip)
+void launch_gather_forces(const int* off, const int* rev, const double* g, int n, long long npairs,
+                          double* forces, hipStream_t s);
+void launch_sum(const double* x, long n, long stride, double* out, hipStream_t s);
+void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream_t s);
+
+}  // namespace mtp

@@ -1,0 +1,264 @@
+// Level-templated MTP kernels.  A translation unit includes one generated level header
+// (struct LvXX with the straight-line program) and then this file, and instantiates the
+// launchers with MTP_DEFINE_LEVEL.
+//
+// Every kernel maps one lane to one atom: the per-atom state (moments, contraction
+// outputs, adjoints) lives in registers with compile-time indices, the neighbour loop of
+// the lane walks the atom's CSR row.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "mtp_device.h"
+#include "mtp_internal.h"
+
+namespace mtp {
+
+constexpr int kLaneBlock = 64;   // one wave per workgroup for the lane-per-atom kernels
+
+// Accessor of a moment vector held in global memory in [entry][atom] layout.
+template <class R>
+struct GlobalMoments {
+  const double* __restrict__ p;
+  long ld;
+  __device__ __forceinline__ R operator()(int e) const { return (R)p[(long)e * ld]; }
+};
+
+template <class R>
+struct RegMoments {
+  const R* m;
+  __device__ __forceinline__ R operator()(int e) const { return m[e]; }
+};
+
+// radial coefficient table staged in LDS
+__device__ __forceinline__ void stage_radial(const SysArgs& a, double* sh) {
+  const int n = a.nsp * a.nsp * a.nmu * a.ncheb;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) sh[k] = a.radial[k];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------- moments
+template <class L, int G>
+__global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
+                                                        double* __restrict__ mout, long ld) {
+  __shared__ double csh[kMaxRadial];
+  stage_radial(a, csh);
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  const int i = i0 + li;
+  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  double m[NG];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) m[e] = 0.0;
+  const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
+  const int zi = clamp_species(a.species[i], a.nsp);
+  const int p0 = a.off[i], p1 = a.off[i + 1];
+  for (int p = p0; p < p1; ++p) {
+    const int j = a.nj[p];
+    int n1, n2, n3;
+    unpack_shift(a.shift[p], n1, n2, n3);
+    double dx, dy, dz;
+    pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2, n3,
+                      a.H, dx, dy, dz);
+    const double r = sqrt(dist2_exact(dx, dy, dz));
+    const int zj = clamp_species(a.species[j], a.nsp);
+    double f[L::NMU];
+    radial_values<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb,
+                                  a.ncheb, f);
+    L::template acc_moments<G>(m, f, dx, dy, dz);
+  }
+#pragma unroll
+  for (int e = 0; e < NG; ++e) mout[(long)(LO + e) * ld + li] = m[e];
+}
+
+// ---------------------------------------------------------------------------- program forward
+template <class L>
+__global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const double* __restrict__ mom, long ld,
+                                                            int i0, int n, const int* __restrict__ species,
+                                                            const double* __restrict__ xi,
+                                                            const double* __restrict__ shift, int nsp,
+                                                            double* __restrict__ e_atom,
+                                                            double* __restrict__ cbar,
+                                                            double* __restrict__ bout) {
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  GlobalMoments<double> M{mom + li, ld};
+  double C[L::NCOMP];
+  L::template fwd<double>(M, C);
+  double Cb[L::NCOMP];
+  const double e = L::template products<double>(C, xi, Cb, bout ? bout + li : nullptr, ld);
+  e_atom[i0 + li] = e + shift[clamp_species(species[i0 + li], nsp)];
+#pragma unroll
+  for (int q = 0; q < L::NCOMP; ++q) cbar[(long)q * ld + li] = Cb[q];
+}
+
+// ---------------------------------------------------------------------------- program reverse
+template <class L, int G>
+__global__ __launch_bounds__(kLaneBlock) void k_program_rev(const double* __restrict__ mom, long ld,
+                                                            int n, const double* __restrict__ cbar,
+                                                            double* __restrict__ mbar) {
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  GlobalMoments<double> M{mom + li, ld};
+  double Cb[L::NCOMP];
+#pragma unroll
+  for (int q = 0; q < L::NCOMP; ++q) Cb[q] = cbar[(long)q * ld + li];
+  double mb[NG];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) mb[e] = 0.0;
+  L::template rev<G>(M, Cb, mb);
+#pragma unroll
+  for (int e = 0; e < NG; ++e) mbar[(long)(LO + e) * ld + li] = mb[e];
+}
+
+// ---------------------------------------------------------------------------- backward pairs
+// g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials.
+template <class L, int G>
+__global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
+                                                         const double* __restrict__ mbar, long ld,
+                                                         double* __restrict__ g, int accumulate,
+                                                         double* __restrict__ wpart) {
+  __shared__ double csh[kMaxRadial];
+  __shared__ double red[kLaneBlock];
+  stage_radial(a, csh);
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  double w[6] = {0, 0, 0, 0, 0, 0};
+  if (li < n) {
+    const int i = i0 + li;
+    double mb[NG];
+#pragma unroll
+    for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li];
+    const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
+    const int zi = clamp_species(a.species[i], a.nsp);
+    const int p0 = a.off[i], p1 = a.off[i + 1];
+    for (int p = p0; p < p1; ++p) {
+      const int j = a.nj[p];
+      int n1, n2, n3;
+      unpack_shift(a.shift[p], n1, n2, n3);
+      double dx, dy, dz;
+      pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2,
+                        n3, a.H, dx, dy, dz);
+      const double r = sqrt(dist2_exact(dx, dy, dz));
+      const int zj = clamp_species(a.species[j], a.nsp);
+      double f[L::NMU], fp[L::NMU];
+      radial<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb,
+                             a.ncheb, f, fp);
+      double gx = 0.0, gy = 0.0, gz = 0.0, u = 0.0;
+      L::template pair_grad<G>(mb, f, fp, dx, dy, dz, gx, gy, gz, u);
+      const double ur = u / r;
+      gx = fma(ur, dx, gx);
+      gy = fma(ur, dy, gy);
+      gz = fma(ur, dz, gz);
+      if (accumulate) {
+        g[3L * p] += gx;
+        g[3L * p + 1] += gy;
+        g[3L * p + 2] += gz;
+      } else {
+        g[3L * p] = gx;
+        g[3L * p + 1] = gy;
+        g[3L * p + 2] = gz;
+      }
+      w[0] -= dx * gx;
+      w[1] -= dy * gy;
+      w[2] -= dz * gz;
+      w[3] -= dx * gy;
+      w[4] -= dx * gz;
+      w[5] -= dy * gz;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double s = block_sum<kLaneBlock>(w[k], red);
+    if (threadIdx.x == 0) wpart[6L * b + k] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------- launchers
+template <class L, int G>
+void launch_moments_g(const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s) {
+  const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+  hipLaunchKernelGGL((k_moments<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, m, ld);
+}
+template <class L, int G>
+void launch_rev_g(const double* m, long ld, int n, const double* cb, double* mb, hipStream_t s) {
+  const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+  hipLaunchKernelGGL((k_program_rev<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, m, ld, n, cb, mb);
+}
+template <class L, int G>
+void launch_backward_g(const SysArgs& a, int i0, int n, const double* mb, long ld, double* g,
+                       int acc, double* wpart, hipStream_t s) {
+  const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+  hipLaunchKernelGGL((k_backward<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, mb, ld, g, acc,
+                     wpart);
+}
+
+template <class L, size_t... Gs>
+void dispatch_moments(int g, const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s,
+                      std::index_sequence<Gs...>) {
+  ((g == (int)Gs ? launch_moments_g<L, (int)Gs>(a, i0, n, m, ld, s) : void()), ...);
+}
+template <class L, size_t... Gs>
+void dispatch_rev(int g, const double* m, long ld, int n, const double* cb, double* mb,
+                  hipStream_t s, std::index_sequence<Gs...>) {
+  ((g == (int)Gs ? launch_rev_g<L, (int)Gs>(m, ld, n, cb, mb, s) : void()), ...);
+}
+template <class L, size_t... Gs>
+void dispatch_backward(int g, const SysArgs& a, int i0, int n, const double* mb, long ld,
+                       double* gout, int acc, double* wpart, hipStream_t s,
+                       std::index_sequence<Gs...>) {
+  ((g == (int)Gs ? launch_backward_g<L, (int)Gs>(a, i0, n, mb, ld, gout, acc, wpart, s) : void()),
+   ...);
+}
+
+template <class L>
+struct LevelImpl {
+  static void moments(int g, const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s) {
+    dispatch_moments<L>(g, a, i0, n, m, ld, s, std::make_index_sequence<L::NGROUP>{});
+  }
+  static void prog_fwd(const double* m, long ld, int i0, int n, const int* species,
+                       const double* xi, const double* shift, int nsp, double* e_atom, double* cbar,
+                       double* bout, hipStream_t s) {
+    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    hipLaunchKernelGGL((k_program_fwd<L>), dim3(nb), dim3(kLaneBlock), 0, s, m, ld, i0, n, species,
+                       xi, shift, nsp, e_atom, cbar, bout);
+  }
+  static void prog_rev(int g, const double* m, long ld, int n, const double* cb, double* mb,
+                       hipStream_t s) {
+    dispatch_rev<L>(g, m, ld, n, cb, mb, s, std::make_index_sequence<L::NGROUP>{});
+  }
+  static void backward(int grp, const SysArgs& a, int i0, int n, const double* mb, long ld,
+                       double* gout, int acc, double* wpart, hipStream_t s) {
+    dispatch_backward<L>(grp, a, i0, n, mb, ld, gout, acc, wpart, s,
+                         std::make_index_sequence<L::NGROUP>{});
+  }
+  static LevelOps ops() {
+    LevelOps o{};
+    o.level = L::LEVEL;
+    o.nmom = L::NMOM;
+    o.ncomp = L::NCOMP;
+    o.nalpha = L::NALPHA;
+    o.nmu = L::NMU;
+    o.maxnu = L::MAXNU;
+    o.ngroup = L::NGROUP;
+    o.triples = L::TRIPLES;
+    o.moments = &moments;
+    o.prog_fwd = &prog_fwd;
+    o.prog_rev = &prog_rev;
+    o.backward = &backward;
+    return o;
+  }
+};
+
+}  // namespace mtp
+
+#define MTP_DEFINE_LEVEL(LV, NUM)                                  \
+  namespace mtp {                                                  \
+  LevelOps level_ops_##NUM() { return LevelImpl<LV>::ops(); }      \
+  }

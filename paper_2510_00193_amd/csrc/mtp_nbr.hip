@@ -1,0 +1,533 @@
+// Canonical periodic neighbour list on the GPU.
+//
+// Output: CSR rows sorted by (j, n1, n2, n3), the mirrored-pair index rev, and the shifts packed
+// as three int8.  A pair is kept iff its squared distance, formed by the fixed binary64
+// expression of pair_displacement/dist2_exact, is below r_cut^2 (strict).  Two candidate
+// generators feed that one predicate:
+//   - cells:  atoms binned in fractional coordinates, bins at least r_cut wide in every
+//             perpendicular direction, so every pair lies in one of the 27 surrounding bins;
+//   - images: every j of the system with the image range that can reach the cutoff,
+//             |s_j,k - s_i,k + n_k| < r_cut |b_k| (+ a rounding margin); used for small or
+//             thin cells, where an atom may see several images of one partner.
+// The candidate sets are supersets of the true set, so both give the same list.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mtp.h"
+#include "mtp_device.h"
+#include "mtp_internal.h"
+
+namespace mtp {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr double kImageMargin = 1e-6;  // fractional-coordinate slack of the image ranges
+
+__device__ __forceinline__ long long make_key(int j, int n1, int n2, int n3) {
+  return ((long long)j << 24) | ((long long)(n1 + 128) << 16) | ((long long)(n2 + 128) << 8) |
+         (long long)(n3 + 128);
+}
+
+__device__ __forceinline__ void frac_of(const double* __restrict__ pos, int i,
+                                        const double* __restrict__ Hinv, double* s) {
+  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = x * Hinv[k] + y * Hinv[3 + k] + z * Hinv[6 + k];
+}
+
+struct PlanArgs {
+  double H[9];
+  double Hinv[9];
+  double reach[3];
+  int nb[3];
+  double rc2;
+};
+
+// ---------------------------------------------------------------- image path
+__global__ void k_frac(const double* __restrict__ pos, const int* __restrict__ species, int nsp, int n,
+                       PlanArgs pa, double* __restrict__ s, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) flag[0] = 1;
+  if (species[i] < 0 || species[i] >= nsp) flag[1] = 1;
+  double f[3];
+  frac_of(pos, i, pa.Hinv, f);
+  s[3 * i] = f[0];
+  s[3 * i + 1] = f[1];
+  s[3 * i + 2] = f[2];
+}
+
+template <bool FILL>
+__device__ __forceinline__ int image_row(int i, const double* __restrict__ pos,
+                                         const double* __restrict__ s, int n, const PlanArgs& pa,
+                                         int* __restrict__ nj, int* __restrict__ shift,
+                                         long long* __restrict__ key, int base,
+                                         int* __restrict__ flag) {
+  const double six = s[3 * i], siy = s[3 * i + 1], siz = s[3 * i + 2];
+  const double rix = pos[3 * i], riy = pos[3 * i + 1], riz = pos[3 * i + 2];
+  int cnt = 0;
+  for (int j = 0; j < n; ++j) {
+    const double ds0 = s[3 * j] - six, ds1 = s[3 * j + 1] - siy, ds2 = s[3 * j + 2] - siz;
+    const int lo0 = (int)ceil(-pa.reach[0] - ds0 - kImageMargin);
+    const int hi0 = (int)floor(pa.reach[0] - ds0 + kImageMargin);
+    const int lo1 = (int)ceil(-pa.reach[1] - ds1 - kImageMargin);
+    const int hi1 = (int)floor(pa.reach[1] - ds1 + kImageMargin);
+    const int lo2 = (int)ceil(-pa.reach[2] - ds2 - kImageMargin);
+    const int hi2 = (int)floor(pa.reach[2] - ds2 + kImageMargin);
+    if (min(lo0, min(lo1, lo2)) < -127 || max(hi0, max(hi1, hi2)) > 127) {
+      // shifts must fit the packed int8 fields; the count pass reports it
+      if (!FILL) flag[2] = 1;
+      continue;
+    }
+    const double rjx = pos[3 * j], rjy = pos[3 * j + 1], rjz = pos[3 * j + 2];
+    for (int n1 = lo0; n1 <= hi0; ++n1)
+      for (int n2 = lo1; n2 <= hi1; ++n2)
+        for (int n3 = lo2; n3 <= hi2; ++n3) {
+          if (j == i && n1 == 0 && n2 == 0 && n3 == 0) continue;
+          double dx, dy, dz;
+          pair_displacement(rix, riy, riz, rjx, rjy, rjz, n1, n2, n3, pa.H, dx, dy, dz);
+          if (dist2_exact(dx, dy, dz) < pa.rc2) {
+            if (FILL) {
+              const int p = base + cnt;
+              nj[p] = j;
+              shift[p] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
+              key[p] = make_key(j, n1, n2, n3);
+            }
+            ++cnt;
+          }
+        }
+  }
+  return cnt;
+}
+
+__global__ void k_image_count(const double* __restrict__ pos, const double* __restrict__ s, int n,
+                              PlanArgs pa, int* __restrict__ counts, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  counts[i] = image_row<false>(i, pos, s, n, pa, nullptr, nullptr, nullptr, 0, flag);
+}
+
+__global__ void k_image_fill(const double* __restrict__ pos, const double* __restrict__ s, int n,
+                             PlanArgs pa, const int* __restrict__ off, int* __restrict__ nj,
+                             int* __restrict__ shift, long long* __restrict__ key) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  image_row<true>(i, pos, s, n, pa, nj, shift, key, off[i], nullptr);
+}
+
+// ---------------------------------------------------------------- cell path
+__global__ void k_bin(const double* __restrict__ pos, const int* __restrict__ species, int nsp, int n,
+                      PlanArgs pa, int* __restrict__ bin, int* __restrict__ img,
+                      int* __restrict__ bincount, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (species[i] < 0 || species[i] >= nsp) flag[1] = 1;
+  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+    flag[0] = 1;
+    bin[i] = 0;
+    img[3 * i] = img[3 * i + 1] = img[3 * i + 2] = 0;
+    atomicAdd(&bincount[0], 1);
+    return;
+  }
+  double f[3];
+  frac_of(pos, i, pa.Hinv, f);
+  int b[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double o = floor(f[k]);
+    double w = f[k] - o;
+    if (w >= 1.0) {
+      w -= 1.0;
+      o += 1.0;
+    }
+    if (fabs(o) > 60.0) {  // image offsets must keep |n| within the packed int8 range
+      flag[2] = 1;
+      o = 0.0;
+    }
+    img[3 * i + k] = (int)o;
+    b[k] = min((int)(w * pa.nb[k]), pa.nb[k] - 1);
+  }
+  const int id = (b[0] * pa.nb[1] + b[1]) * pa.nb[2] + b[2];
+  bin[i] = id;
+  atomicAdd(&bincount[id], 1);
+}
+
+__global__ void k_bin_scatter(int n, const int* __restrict__ bin, const int* __restrict__ binstart,
+                              int* __restrict__ binfill, int* __restrict__ binatoms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int id = bin[i];
+  const int slot = atomicAdd(&binfill[id], 1);
+  binatoms[binstart[id] + slot] = i;
+}
+
+template <bool FILL>
+__device__ __forceinline__ int cell_row(int i, const double* __restrict__ pos, const PlanArgs& pa,
+                                        const int* __restrict__ bin, const int* __restrict__ img,
+                                        const int* __restrict__ binstart,
+                                        const int* __restrict__ binatoms, long long* __restrict__ key,
+                                        int* __restrict__ rowid, int base) {
+  const int id = bin[i];
+  const int b2 = id % pa.nb[2];
+  const int b1 = (id / pa.nb[2]) % pa.nb[1];
+  const int b0 = id / (pa.nb[2] * pa.nb[1]);
+  const int oi0 = img[3 * i], oi1 = img[3 * i + 1], oi2 = img[3 * i + 2];
+  const double rix = pos[3 * i], riy = pos[3 * i + 1], riz = pos[3 * i + 2];
+  int cnt = 0;
+  for (int d0 = -1; d0 <= 1; ++d0) {
+    int c0 = b0 + d0, w0 = 0;
+    if (c0 < 0) { c0 += pa.nb[0]; w0 = -1; }
+    if (c0 >= pa.nb[0]) { c0 -= pa.nb[0]; w0 = 1; }
+    if (pa.nb[0] == 1) { c0 = 0; w0 = d0; }
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      int c1 = b1 + d1, w1 = 0;
+      if (c1 < 0) { c1 += pa.nb[1]; w1 = -1; }
+      if (c1 >= pa.nb[1]) { c1 -= pa.nb[1]; w1 = 1; }
+      if (pa.nb[1] == 1) { c1 = 0; w1 = d1; }
+      for (int d2 = -1; d2 <= 1; ++d2) {
+        int c2 = b2 + d2, w2 = 0;
+        if (c2 < 0) { c2 += pa.nb[2]; w2 = -1; }
+        if (c2 >= pa.nb[2]) { c2 -= pa.nb[2]; w2 = 1; }
+        if (pa.nb[2] == 1) { c2 = 0; w2 = d2; }
+        const int cid = (c0 * pa.nb[1] + c1) * pa.nb[2] + c2;
+        const int q0 = binstart[cid], q1 = binstart[cid + 1];
+        for (int q = q0; q < q1; ++q) {
+          const int j = binatoms[q];
+          const int n1 = w0 + oi0 - img[3 * j];
+          const int n2 = w1 + oi1 - img[3 * j + 1];
+          const int n3 = w2 + oi2 - img[3 * j + 2];
+          if (j == i && n1 == 0 && n2 == 0 && n3 == 0) continue;
+          double dx, dy, dz;
+          pair_displacement(rix, riy, riz, pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], n1, n2, n3,
+                            pa.H, dx, dy, dz);
+          if (dist2_exact(dx, dy, dz) < pa.rc2) {
+            if (FILL) {
+              key[base + cnt] = make_key(j, n1, n2, n3);
+              rowid[base + cnt] = i;
+            }
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  return cnt;
+}
+
+__global__ void k_cell_count(const double* __restrict__ pos, int n, PlanArgs pa,
+                             const int* __restrict__ bin, const int* __restrict__ img,
+                             const int* __restrict__ binstart, const int* __restrict__ binatoms,
+                             int* __restrict__ counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  counts[i] = cell_row<false>(i, pos, pa, bin, img, binstart, binatoms, nullptr, nullptr, 0);
+}
+
+__global__ void k_cell_fill(const double* __restrict__ pos, int n, PlanArgs pa,
+                            const int* __restrict__ bin, const int* __restrict__ img,
+                            const int* __restrict__ binstart, const int* __restrict__ binatoms,
+                            const int* __restrict__ off, long long* __restrict__ key,
+                            int* __restrict__ rowid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cell_row<true>(i, pos, pa, bin, img, binstart, binatoms, key, rowid, off[i]);
+}
+
+// rank of each key inside its row (keys are distinct) -> sorted position
+__global__ void k_row_sort(long long total, const int* __restrict__ off,
+                           const int* __restrict__ rowid, const long long* __restrict__ key,
+                           long long* __restrict__ skey, int* __restrict__ nj,
+                           int* __restrict__ shift) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  const int i = rowid[p];
+  const int q0 = off[i], q1 = off[i + 1];
+  const long long k = key[p];
+  int rank = 0;
+  for (int q = q0; q < q1; ++q) rank += key[q] < k;
+  const int dst = q0 + rank;
+  skey[dst] = k;
+  nj[dst] = (int)(k >> 24);
+  const int n1 = (int)((k >> 16) & 0xFF) - 128, n2 = (int)((k >> 8) & 0xFF) - 128,
+            n3 = (int)(k & 0xFF) - 128;
+  shift[dst] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
+}
+
+// row id of every pair (image path writes rows in order; rev needs the centre of each pair)
+__global__ void k_rowid(int n, const int* __restrict__ off, int* __restrict__ rowid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int p = off[i]; p < off[i + 1]; ++p) rowid[p] = i;
+}
+
+__global__ void k_rev(long long total, const int* __restrict__ off, const int* __restrict__ rowid,
+                      const long long* __restrict__ skey, int* __restrict__ rev) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  const long long k = skey[p];
+  const int i = rowid[p];
+  const int j = (int)(k >> 24);
+  const int n1 = (int)((k >> 16) & 0xFF) - 128, n2 = (int)((k >> 8) & 0xFF) - 128,
+            n3 = (int)(k & 0xFF) - 128;
+  const long long want = make_key(i, -n1, -n2, -n3);
+  int lo = off[j], hi = off[j + 1] - 1, found = -1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const long long v = skey[mid];
+    if (v == want) {
+      found = mid;
+      break;
+    }
+    if (v < want) lo = mid + 1; else hi = mid - 1;
+  }
+  rev[p] = found;
+}
+
+// ---------------------------------------------------------------- exclusive scan (int)
+constexpr int kScanPer = 8;
+constexpr int kScanBlock = kNT * kScanPer;
+
+__global__ void k_scan_local(const int* __restrict__ in, int n, int* __restrict__ out,
+                             long long* __restrict__ bsum) {
+  __shared__ long long sh[kNT];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  long long v[kScanPer];
+  long long acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    acc += v[k];
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 1; s < kNT; s <<= 1) {
+    long long t = threadIdx.x >= s ? sh[threadIdx.x - s] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  long long run = sh[threadIdx.x] - acc;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) out[base + k] = (int)run;
+    run += v[k];
+  }
+  if (threadIdx.x == kNT - 1) bsum[blockIdx.x] = sh[kNT - 1];
+}
+
+__global__ void k_scan_blocks(long long* __restrict__ bsum, int nb, long long* __restrict__ total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    long long run = 0;
+    for (int b = 0; b < nb; ++b) {
+      const long long t = bsum[b];
+      bsum[b] = run;
+      run += t;
+    }
+    total[0] = run;
+  }
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int n, const long long* __restrict__ bsum,
+                           const long long* __restrict__ total, int write_total) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int)(out[i] + bsum[i / kScanBlock]);
+  if (write_total && i == 0) out[n] = (int)total[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- workspace
+struct NbrWork {
+  std::vector<void*> bufs;
+  size_t cap[16] = {0};
+  void* ptr[16] = {nullptr};
+  ~NbrWork() {
+    for (int k = 0; k < 16; ++k)
+      if (ptr[k]) (void)hipFree(ptr[k]);
+  }
+  template <class T>
+  T* get(int slot, size_t n) {
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (cap[slot] < bytes) {
+      if (ptr[slot]) (void)hipFree(ptr[slot]);
+      ptr[slot] = nullptr;
+      cap[slot] = 0;
+      if (hipMalloc(&ptr[slot], bytes) != hipSuccess) return nullptr;
+      cap[slot] = bytes;
+    }
+    return (T*)ptr[slot];
+  }
+  PlanArgs pa;
+};
+
+NbrWork* nbr_work_create() { return new NbrWork(); }
+void nbr_work_destroy(NbrWork* w) { delete w; }
+
+enum Slot { S_FRAC, S_BIN, S_IMG, S_BINCNT, S_BINSTART, S_BINFILL, S_BINATOMS, S_COUNTS, S_BSUM,
+            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG };
+
+static void inv3(const double* H, double* I, double* det) {
+  const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7],
+               k = H[8];
+  const double A = e * k - f * h, B = -(d * k - f * g), C = d * h - e * g;
+  *det = a * A + b * B + c * C;
+  const double id = 1.0 / *det;
+  I[0] = A * id; I[1] = -(b * k - c * h) * id; I[2] = (b * f - c * e) * id;
+  I[3] = B * id; I[4] = (a * k - c * g) * id;  I[5] = -(a * f - c * d) * id;
+  I[6] = C * id; I[7] = -(a * h - b * g) * id; I[8] = (a * e - b * d) * id;
+}
+
+void nbr_plan(const double* H, double rcut, NbrPlan* plan, int* status) {
+  double det;
+  inv3(H, plan->Hinv, &det);
+  *status = 0;
+  if (!(fabs(det) > 1e-300) || !isfinite(det)) {
+    *status = MTP_ERR_CELL;
+    return;
+  }
+  double width[3];
+  for (int k = 0; k < 3; ++k) {
+    // b_k = column k of H^-1 (rows of H^-T); perpendicular width 1/|b_k|
+    const double bx = plan->Hinv[k], by = plan->Hinv[3 + k], bz = plan->Hinv[6 + k];
+    const double bn = sqrt(bx * bx + by * by + bz * bz);
+    plan->reach[k] = rcut * bn;
+    width[k] = 1.0 / bn;
+  }
+  const double need = rcut * (1.0 + 1e-9) + 1e-12;
+  plan->cells = true;
+  long long nbins = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (width[k] < need) plan->cells = false;
+    plan->nb[k] = std::max(1, (int)floor(width[k] / need));
+    plan->nb[k] = std::min(plan->nb[k], 1 << 10);
+    nbins *= plan->nb[k];
+  }
+  if (nbins > (1LL << 24)) plan->cells = false;
+}
+
+static void fill_args(PlanArgs& pa, const NbrPlan& plan, const double* H, double rcut) {
+  for (int k = 0; k < 9; ++k) {
+    pa.H[k] = H[k];
+    pa.Hinv[k] = plan.Hinv[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    pa.reach[k] = plan.reach[k];
+    pa.nb[k] = plan.nb[k];
+  }
+  pa.rc2 = rcut * rcut;
+}
+
+static int scan_counts(NbrWork* w, const int* counts, int n, int* off, long long* total_host,
+                       hipStream_t s) {
+  const int nb = (n + kScanBlock - 1) / kScanBlock;
+  long long* bsum = w->get<long long>(S_BSUM, nb + 1);
+  long long* tot = w->get<long long>(S_TOTAL, 1);
+  if (!bsum || !tot) return MTP_ERR_OOM;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kNT), 0, s, counts, n, off, bsum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1), 0, s, bsum, nb, tot);
+    hipLaunchKernelGGL(k_scan_add, dim3((n + kNT - 1) / kNT), dim3(kNT), 0, s, off, n, bsum, tot, 1);
+  } else {
+    (void)hipMemsetAsync(off, 0, sizeof(int), s);
+    (void)hipMemsetAsync(tot, 0, sizeof(long long), s);
+  }
+  if (total_host) {
+    if (hipMemcpyAsync(total_host, tot, sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return MTP_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
+  }
+  return 0;
+}
+
+int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int nsp, int n,
+              const double* H, double rcut, NbrWork* w, int* off, long long* total, int* flags,
+              hipStream_t s) {
+  PlanArgs& pa = w->pa;
+  fill_args(pa, plan, H, rcut);
+  int* counts = w->get<int>(S_COUNTS, n);
+  int* flag = w->get<int>(S_FLAG, 4);
+  if (!counts || !flag) return MTP_ERR_OOM;
+  (void)hipMemsetAsync(flag, 0, 4 * sizeof(int), s);
+  const int gb = (n + kNT - 1) / kNT;
+  if (plan.cells) {
+    const int nbins = plan.nb[0] * plan.nb[1] * plan.nb[2];
+    int* bin = w->get<int>(S_BIN, n);
+    int* img = w->get<int>(S_IMG, 3L * n);
+    int* bincnt = w->get<int>(S_BINCNT, nbins);
+    int* binstart = w->get<int>(S_BINSTART, nbins + 1);
+    int* binfill = w->get<int>(S_BINFILL, nbins);
+    int* binatoms = w->get<int>(S_BINATOMS, n);
+    if (!bin || !img || !bincnt || !binstart || !binfill || !binatoms) return MTP_ERR_OOM;
+    (void)hipMemsetAsync(bincnt, 0, sizeof(int) * nbins, s);
+    (void)hipMemsetAsync(binfill, 0, sizeof(int) * nbins, s);
+    if (n > 0) hipLaunchKernelGGL(k_bin, dim3(gb), dim3(kNT), 0, s, pos, species, nsp, n, pa, bin, img, bincnt,
+                         flag);
+    int rc = scan_counts(w, bincnt, nbins, binstart, nullptr, s);
+    if (rc) return rc;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(kNT), 0, s, n, bin, binstart, binfill, binatoms);
+      hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart,
+                         binatoms, counts);
+    }
+  } else {
+    double* sfrac = w->get<double>(S_FRAC, 3L * n);
+    if (!sfrac) return MTP_ERR_OOM;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_frac, dim3(gb), dim3(kNT), 0, s, pos, species, nsp, n, pa, sfrac, flag);
+      hipLaunchKernelGGL(k_image_count, dim3(gb), dim3(kNT), 0, s, pos, sfrac, n, pa, counts, flag);
+    }
+  }
+  int rc = scan_counts(w, counts, n, off, total, s);
+  if (rc) return rc;
+  if (hipMemcpyAsync(flags, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return MTP_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
+  return 0;
+}
+
+int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, double rcut,
+             NbrWork* w, const int* off, int* nj, int* shift, int* rev, long long total,
+             hipStream_t s) {
+  PlanArgs& pa = w->pa;
+  fill_args(pa, plan, H, rcut);
+  const int gb = (n + kNT - 1) / kNT;
+  const int gp = (int)((total + kNT - 1) / kNT);
+  long long* skey = w->get<long long>(S_SKEY, total);
+  int* rowid = w->get<int>(S_ROWID, total);
+  if (!skey || !rowid) return MTP_ERR_OOM;
+  if (plan.cells) {
+    long long* key = w->get<long long>(S_KEY, total);
+    if (!key) return MTP_ERR_OOM;
+    int* bin = w->get<int>(S_BIN, n);
+    int* img = w->get<int>(S_IMG, 3L * n);
+    int* binstart = w->get<int>(S_BINSTART, 1);
+    int* binatoms = w->get<int>(S_BINATOMS, n);
+    if (n > 0) {
+      hipLaunchKernelGGL(k_cell_fill, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart,
+                         binatoms, off, key, rowid);
+      if (total > 0)
+        hipLaunchKernelGGL(k_row_sort, dim3(gp), dim3(kNT), 0, s, total, off, rowid, key, skey, nj,
+                           shift);
+    }
+  } else {
+    double* sfrac = w->get<double>(S_FRAC, 3L * n);
+    if (n > 0) {
+      hipLaunchKernelGGL(k_image_fill, dim3(gb), dim3(kNT), 0, s, pos, sfrac, n, pa, off, nj, shift,
+                         skey);
+      if (rev) hipLaunchKernelGGL(k_rowid, dim3(gb), dim3(kNT), 0, s, n, off, rowid);
+    }
+  }
+  if (rev && total > 0)
+    hipLaunchKernelGGL(k_rev, dim3(gp), dim3(kNT), 0, s, total, off, rowid, skey, rev);
+  if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
+  return 0;
+}
+
+}  // namespace mtp

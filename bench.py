@@ -1,0 +1,174 @@
+"""Benchmark of the MTP hot path on one MI355X.
+
+One step = one pass of the hot path over the 1,024,000-atom level-16 bcc
+workload: canonical neighbour-list rebuild, then energy, forces and virial
+(float64).  Prints one JSON line.  Extra fields report the evaluation on a
+prebuilt list, per-kernel times and the roofline of the dominant kernel.
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+METRIC = "atom-steps/s (E+F+virial) at 1M atoms; batched param-grad configs/s vs plain"
+
+
+def flop_model(info, n_cheb):
+    """Algorithmic flops per unit of each kernel class (FMA = 2), from the model tables."""
+    C, nmu, T, nalpha, maxnu = (info["n_moments"], info["n_mu"], info["n_products"], info["n_alpha"],
+                                info["max_nu"])
+    mono = (maxnu + 1) * (maxnu + 2) * (maxnu + 3) // 6 - 1
+    return {
+        "moments": ("pair", 3 * n_cheb + 2 * nmu * n_cheb + mono + 2 * C),
+        "program_forward": ("atom", 3 * T + 2 * nalpha),
+        "program_reverse": ("atom", 6 * T),
+        "pair_backward": ("pair", 6 * n_cheb + 2 * nmu * n_cheb + 8 * C + 10 * nmu + 22),
+    }
+
+
+def cpu_baseline(params, target_s=12.0):
+    """The oracle on a bounded sample of the same workload: 10x10x10 bcc cells (2000 atoms)
+    drawn with the same recipe, neighbour list + E + F + virial, repeated to ~target_s."""
+    import torch
+    from oracle import mtp as om
+    from oracle import neighbors as onb
+    rng = np.random.default_rng(3)
+    sites, cell = wl.bcc_sites(10, 10, 10, 3.16)
+    pos = wl.jitter_wrap(sites, cell, 0.1, rng)
+    s = wl.Structure(pos, np.zeros(len(pos), np.int32), cell)
+    model = om.Model.from_params(params)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        nl = onb.neighbor_csr(s.pos, s.cell, params.r_cut)
+        om.energy_forces_virial(model, s, nl)
+        reps += 1
+        if time.perf_counter() - t0 >= target_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": s.n_atoms * reps / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} x (neighbour list + E/F/virial) of a 2000-atom 10x10x10 bcc cell, "
+                      f"same recipe and level-16 coefficients, {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--rep", type=int, default=80, help="bcc repeat (80 -> 1,024,000 atoms)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        return 2
+
+    import torch
+    from paper_2510_00193_amd import Potential, level_info
+
+    level = 16
+    info = level_info(level)
+    w = wl.workload(3, info["n_alpha"], info["n_mu"], small={"rep": (args.rep,) * 3})
+    (s,) = w["structures"]
+    params = w["params"]
+    n = s.n_atoms
+    dev = torch.device("cuda:0")
+    pos = torch.as_tensor(s.pos, device=dev)
+    sp = torch.as_tensor(s.species, device=dev)
+    pot = Potential.from_params(params)
+    print(f"# workload bcc {args.rep}^3 x2 = {n} atoms, level {level}", file=sys.stderr, flush=True)
+
+    def step():
+        return pot.compute(pos, sp, s.cell)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    pot.profile(True)
+    pot.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pot.profile_read()
+    pot.profile(False)
+    ms_step = dt * 1e3 / args.steps
+    value = n * args.steps / dt
+    print(f"# full step {ms_step:.3f} ms", file=sys.stderr, flush=True)
+
+    # evaluation on a prebuilt list (the list is reused, as between rebuilds in MD)
+    nl = pot.neighbors(pos, sp, s.cell)
+    torch.cuda.synchronize()
+    n_pairs = nl.n_pairs
+    for _ in range(2):
+        pot.compute(pos, sp, s.cell, nlist=nl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pot.compute(pos, sp, s.cell, nlist=nl)
+    torch.cuda.synchronize()
+    dt_eval = time.perf_counter() - t0
+    eval_rate = n * args.steps / dt_eval
+
+    # roofline of the dominant compute kernel (algorithmic flops / average launch time)
+    fm = flop_model(info, params.n_cheb)
+    kernels = {}
+    for name, (ms, launches) in prof.items():
+        if launches:
+            kernels[name] = {"avg_ms": ms / launches, "launches_per_step": launches / args.steps,
+                             "ms_per_step": ms / args.steps}
+    dom = max((k for k in kernels if k in fm), key=lambda k: kernels[k]["ms_per_step"])
+    unit, per_unit = fm[dom]
+    units_per_step = n_pairs if unit == "pair" else n
+    flops_per_launch = per_unit * units_per_step / kernels[dom]["launches_per_step"]
+    achieved = flops_per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                "flops_per_unit": per_unit, "unit_of_work": unit, "launch_avg_ms": kernels[dom]["avg_ms"]}
+    total_flops = sum(fm[k][1] * (n_pairs if fm[k][0] == "pair" else n) for k in fm)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"bcc-{args.rep}x{args.rep}x{args.rep}-L16: {n} atoms, level 16, 1 species, "
+                               "8 Chebyshev functions, r_cut 5.0; step = neighbour rebuild + E/F/virial",
+                   "atoms": n, "pairs": n_pairs, "level": level},
+        "roofline": roofline,
+        "eval_only": {"value": eval_rate, "unit": "atom-steps/s", "ms_per_step": dt_eval * 1e3 / args.steps,
+                      "flops_per_step": total_flops,
+                      "fp64_tflops": total_flops / (dt_eval / args.steps) / 1e12},
+        "kernels": kernels,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(params)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -102,6 +102,12 @@ typedef struct {
 /* Number of compiled levels and their values (host array of at least 32 ints). */
 int mtp_levels(int* n, int* levels);
 
+/* Sizes of a compiled level without creating a model.  info (host, n_info ints) receives
+ * [n_alpha, n_mu, n_moments, n_components, n_products, max_nu, n_groups]: basis functions,
+ * radial functions, stored moment components, connected contractions, weighted products
+ * of the compiled contraction program, largest tensor rank, moment groups per pass. */
+int mtp_level_info(int level, int* info, int n_info);
+
 /* Create a model: copies the parameters to the device.  Synchronizes. */
 int mtp_create(const mtp_params* p, mtp_model** out);
 void mtp_destroy(mtp_model* m);
@@ -146,6 +152,15 @@ int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const do
 int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double ebar,
                    const double* fbar, double* d_linear, double* d_radial, double* d_shift,
                    void* stream);
+
+/* Per-kernel timing with HIP events recorded on the caller's stream around every launch of the
+ * hot path (for benchmarks; off by default).  mtp_profile_read synchronizes the recorded
+ * events, adds them to the totals, and reports kernel class k: its name (static string),
+ * accumulated milliseconds and launch count; MTP_ERR_ARG past the last class.
+ * mtp_profile_reset clears the totals. */
+int mtp_profile(mtp_model* m, int enable);
+int mtp_profile_read(mtp_model* m, int k, const char** name, double* total_ms, long long* launches);
+int mtp_profile_reset(mtp_model* m);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ MTP_FP32_MOMENTS = 1
 MTP_GRADE_FP64 = 0
 MTP_GRADE_FP32SPLIT = 1
 
-EXPORTS = ("mtp_levels", "mtp_create", "mtp_destroy", "mtp_last_error", "mtp_sizes", "mtp_set_params",
+EXPORTS = ("mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset", "mtp_create", "mtp_destroy", "mtp_last_error", "mtp_sizes", "mtp_set_params",
            "mtp_neighbors", "mtp_compute", "mtp_grade", "mtp_param_grad")
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -89,6 +89,10 @@ def open_library(path: str):
     lib = ctypes.CDLL(path)
     vp, i, ll, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double
     lib.mtp_levels.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.mtp_level_info.argtypes = [i, ctypes.POINTER(i), i]
+    lib.mtp_profile.argtypes = [vp, i]
+    lib.mtp_profile_reset.argtypes = [vp]
+    lib.mtp_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(d), ctypes.POINTER(ll)]
     lib.mtp_create.argtypes = [ctypes.POINTER(MtpParams), ctypes.POINTER(vp)]
     lib.mtp_destroy.argtypes = [vp]
     lib.mtp_destroy.restype = None
@@ -102,7 +106,8 @@ def open_library(path: str):
     if hasattr(lib, "mtp_param_grad"):
         lib.mtp_param_grad.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), d, vp, vp, vp,
                                        vp, vp]
-    for name in ("mtp_levels", "mtp_create", "mtp_sizes", "mtp_set_params", "mtp_neighbors", "mtp_compute",
+    for name in ("mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset",
+                 "mtp_create", "mtp_sizes", "mtp_set_params", "mtp_neighbors", "mtp_compute",
                  "mtp_grade", "mtp_param_grad"):
         if hasattr(lib, name):
             getattr(lib, name).restype = ctypes.c_int

@@ -64,6 +64,17 @@ def compiled_levels():
     return [buf[k] for k in range(n.value)]
 
 
+LEVEL_INFO_KEYS = ("n_alpha", "n_mu", "n_moments", "n_components", "n_products", "max_nu", "n_groups")
+
+
+def level_info(level):
+    """Sizes of a compiled level (no GPU needed)."""
+    lib = _lib.load()
+    buf = (ctypes.c_int * len(LEVEL_INFO_KEYS))()
+    check(lib.mtp_level_info(int(level), buf, len(LEVEL_INFO_KEYS)))
+    return dict(zip(LEVEL_INFO_KEYS, list(buf)))
+
+
 class Potential:
     """One MTP model on the current GPU."""
 
@@ -102,6 +113,28 @@ class Potential:
             self.close()
         except Exception:
             pass
+
+    # ------------------------------------------------------------------ profiling
+    def profile(self, enable=True):
+        check(self._lib.mtp_profile(self._h, 1 if enable else 0))
+
+    def profile_reset(self):
+        check(self._lib.mtp_profile_reset(self._h))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} accumulated since the last reset (synchronizes)."""
+        out = {}
+        k = 0
+        while True:
+            name = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            code = self._lib.mtp_profile_read(self._h, k, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(n))
+            if code != _lib.MTP_OK:
+                break
+            out[name.value.decode()] = (ms.value, n.value)
+            k += 1
+        return out
 
     # ------------------------------------------------------------------ helpers
     def _system(self, pos, species, cell):

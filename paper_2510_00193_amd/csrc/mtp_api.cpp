@@ -66,9 +66,98 @@ int DevBuf::reserve(size_t n) {
   return MTP_OK;
 }
 
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+Profiler::~Profiler() {
+  for (auto& r : pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Profiler* p_, int cls_, hipStream_t s_) : p(p_), cls(cls_), s(s_) {
+  if (p && p->on) {
+    a = p->take();
+    if (a) (void)hipEventRecord(a, s);
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = p->take();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  p->pending.push_back({cls, a, b});
+}
+
+static const char* kProfNames[P_NCLASS] = {"neighbor_build", "moments", "program_forward",
+                                           "program_reverse", "pair_backward", "force_gather",
+                                           "reductions", "grade_gemm", "tangent", "adjoint_pairs",
+                                           "batch"};
+
 extern "C" {
 
 const char* mtp_last_error(void) { return g_err.c_str(); }
+
+int mtp_level_info(int level, int* info, int n_info) {
+  LevelOps ops;
+  if (!find_level(level, &ops))
+    return mtp_fail(MTP_ERR_LEVEL, "level " + std::to_string(level) + " is not compiled");
+  if (!info || n_info < 0) return mtp_fail(MTP_ERR_ARG, "null info");
+  const int vals[7] = {ops.nalpha, ops.nmu, ops.nmom, ops.ncomp, ops.triples, ops.maxnu, ops.ngroup};
+  for (int k = 0; k < n_info && k < 7; ++k) info[k] = vals[k];
+  return MTP_OK;
+}
+
+int mtp_profile(mtp_model* m, int enable) {
+  if (!m) return mtp_fail(MTP_ERR_ARG, "null model");
+  m->prof.on = enable != 0;
+  return MTP_OK;
+}
+
+int mtp_profile_reset(mtp_model* m) {
+  if (!m) return mtp_fail(MTP_ERR_ARG, "null model");
+  for (auto& r : m->prof.pending) {
+    (void)hipEventSynchronize(r.b);
+    m->prof.pool.push_back(r.a);
+    m->prof.pool.push_back(r.b);
+  }
+  m->prof.pending.clear();
+  for (int k = 0; k < P_NCLASS; ++k) {
+    m->prof.ms[k] = 0.0;
+    m->prof.launches[k] = 0;
+  }
+  return MTP_OK;
+}
+
+int mtp_profile_read(mtp_model* m, int k, const char** name, double* total_ms, long long* launches) {
+  if (!m) return mtp_fail(MTP_ERR_ARG, "null model");
+  if (k < 0 || k >= P_NCLASS) return mtp_fail(MTP_ERR_ARG, "no such kernel class");
+  for (auto& r : m->prof.pending) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    m->prof.ms[r.cls] += ms;
+    m->prof.launches[r.cls] += 1;
+    m->prof.pool.push_back(r.a);
+    m->prof.pool.push_back(r.b);
+  }
+  m->prof.pending.clear();
+  if (name) *name = kProfNames[k];
+  if (total_ms) *total_ms = m->prof.ms[k];
+  if (launches) *launches = m->prof.launches[k];
+  return MTP_OK;
+}
 
 int mtp_levels(int* n, int* levels) {
   if (!n) return mtp_fail(MTP_ERR_ARG, "n is NULL");
@@ -182,6 +271,7 @@ int build_neighbors(mtp_model* m, const mtp_system* sys, int* off, int* nj, int*
   }
   if (!plan.cells && n > kMaxAllPairsAtoms)
     return mtp_fail(MTP_ERR_CELL, "cell thinner than r_cut for a system too large for the all-pairs search");
+  ProfScope ps(&m->prof, P_NBR, s);
   long long total = 0;
   int flags[4] = {0, 0, 0, 0};
   rc = nbr_count(plan, sys->pos, sys->species, m->nsp, n, sys->cell, m->rcut, m->nbr, off, &total,
@@ -281,13 +371,24 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
   long blk = 0;
   for (int i0 = 0; i0 < n; i0 += chunk) {
     const int cn = std::min(chunk, n - i0);
-    for (int g = 0; g < L.ngroup; ++g) L.moments(g, a, i0, cn, mom, ld, s);
-    L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
-               (const double*)m->shift.p, m->nsp, e_atom, cbar, bvals, s);
+    for (int g = 0; g < L.ngroup; ++g) {
+      ProfScope ps(&m->prof, P_MOMENTS, s);
+      L.moments(g, a, i0, cn, mom, ld, s);
+    }
+    {
+      ProfScope ps(&m->prof, P_PROG_FWD, s);
+      L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
+                 (const double*)m->shift.p, m->nsp, e_atom, cbar, bvals, s);
+    }
     if (backward) {
-      for (int g = 0; g < L.ngroup; ++g) L.prog_rev(g, mom, ld, cn, cbar, mbar, s);
-      for (int g = 0; g < L.ngroup; ++g)
+      for (int g = 0; g < L.ngroup; ++g) {
+        ProfScope ps(&m->prof, P_PROG_REV, s);
+        L.prog_rev(g, mom, ld, cn, cbar, mbar, s);
+      }
+      for (int g = 0; g < L.ngroup; ++g) {
+        ProfScope ps(&m->prof, P_BACKWARD, s);
         L.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, s);
+      }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
     }
   }
@@ -314,9 +415,16 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
   if (n > 0) {
     if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s))) return rc;
   }
-  if (energy) launch_sum(ea, n, 1, energy, s);
-  if (forces && n > 0) launch_gather_forces(use.off, use.rev, (const double*)m->g.p, n, use.n_pairs, forces, s);
+  if (energy) {
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_sum(ea, n, 1, energy, s);
+  }
+  if (forces && n > 0) {
+    ProfScope ps(&m->prof, P_GATHER, s);
+    launch_gather_forces(use.off, use.rev, (const double*)m->g.p, n, use.n_pairs, forces, s);
+  }
   if (virial) {
+    ProfScope ps(&m->prof, P_REDUCE, s);
     if (n > 0)
       launch_sum_virial((const double*)m->wpart.p, m->wblocks, virial, s);
     else

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "mtp.h"
 #include "mtp_internal.h"
@@ -22,6 +23,31 @@ struct DevBuf {
   int reserve(size_t n);
 };
 
+// Kernel classes timed by the profiler.
+enum ProfClass { P_NBR = 0, P_MOMENTS, P_PROG_FWD, P_PROG_REV, P_BACKWARD, P_GATHER, P_REDUCE, P_GRADE,
+                 P_TANGENT, P_ADJ_PAIRS, P_BATCH, P_NCLASS };
+
+struct Profiler {
+  bool on = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  double ms[P_NCLASS] = {0};
+  long long launches[P_NCLASS] = {0};
+  hipEvent_t take();
+  ~Profiler();
+};
+
+// Brackets the launches of one kernel class with events when profiling is on.
+struct ProfScope {
+  Profiler* p;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(Profiler* p_, int cls_, hipStream_t s_);
+  ~ProfScope();
+};
+
 struct mtp_model {
   mtp::LevelOps ops;
   int nsp = 0, ncheb = 0, precision = 0, chunk = 0;
@@ -33,6 +59,7 @@ struct mtp_model {
   DevBuf scratch;
   long wblocks = 0;
   mtp::NbrWork* nbr = nullptr;
+  Profiler prof;
 };
 
 int mtp_fail(int code, const std::string& msg);

@@ -50,7 +50,7 @@ def generate(levels):
     for lv in levels:
         write_level(lv, GEN, LEVELS[lv])
         _write_if_changed(os.path.join(GEN, f"mtp_L{lv}.hip"),
-                          f'// Generated: kernels of level {lv}.\n#include <hip/hip_runtime.h>\n#include "gen/mtp_L{lv}.inc"\n'
+                          f'// Generated: kernels of level {lv}.\n#include "mtp_device.h"\n#include "gen/mtp_L{lv}.inc"\n'
                           f'#include "mtp_level_impl.h"\nMTP_DEFINE_LEVEL(Lv{lv}, {lv})\n')
     _write_if_changed(os.path.join(GEN, "levels.inc"),
                       "".join(f"MTP_LEVEL({lv})\n" for lv in levels))
@@ -66,12 +66,25 @@ def _compile(src, obj):
 
 
 def sources(levels):
-    out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_nbr.hip", "mtp_common.hip")]
+    out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_nbr.hip", "mtp_common.hip", "mtp_grade.hip")]
     out += [os.path.join(GEN, f"mtp_L{lv}.hip") for lv in levels]
     return out
 
 
-def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True):
+def _deps_mtime(src):
+    """Newest mtime among a source, the shared headers and (for a level unit) its program."""
+    paths = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    paths.append(os.path.join(INCLUDE, "mtp.h"))
+    base = os.path.basename(src)
+    if base.startswith("mtp_L") and base.endswith(".hip"):
+        paths.append(os.path.join(GEN, base[:-4] + ".inc"))
+    if base == "mtp_api.cpp":
+        paths.append(os.path.join(GEN, "levels.inc"))
+    return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
+
+
+def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, incremental=False):
+    """Compile every source (incremental=True skips objects newer than their inputs)."""
     levels = tuple(sorted(levels))
     generate(levels)
     os.makedirs(OBJ, exist_ok=True)
@@ -82,6 +95,9 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True):
         futs = {}
         for src in srcs:
             obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+            if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= _deps_mtime(src):
+                objs.append(obj)
+                continue
             lang = ["-x", "hip"] if src.endswith(".cpp") else []
             futs[ex.submit(_compile_lang, src, obj, lang)] = src
         for fut in cf.as_completed(futs):
@@ -113,9 +129,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--levels", default=",".join(str(l) for l in DEFAULT_LEVELS))
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true", help="reuse objects newer than their inputs")
     args = ap.parse_args(argv)
     levels = [int(x) for x in args.levels.split(",") if x]
-    build(levels, args.jobs)
+    build(levels, args.jobs, incremental=args.incremental)
 
 
 if __name__ == "__main__":

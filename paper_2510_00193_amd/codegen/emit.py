@@ -246,6 +246,7 @@ def _emit_components_reverse(w: _W, prog: Program, groups):
                 continue
             w(f"{{  // contraction {blk.q}")
             w.push()
+            w("MTP_BLOCK_FENCE();")
             for e in blk.entries:
                 w(f"const R me{e} = M({e});")
             w(f"const R cb = Cb[{blk.q}];")
@@ -315,7 +316,7 @@ def _emit_products(w: _W, prog: Program):
         else:
             children[parent].append(a)
     w("// E_i contribution sum_alpha xi_alpha B_alpha; Cb_q = dE_i/dC_q; B written when Bo != nullptr")
-    w("template <class R>")
+    w("template <bool WB, class R>")
     w("static __device__ __forceinline__ double products(const R* __restrict__ C, const double* __restrict__ xi,")
     w("    R* __restrict__ Cb, double* __restrict__ Bo, long ldb) {")
     w.push()
@@ -334,7 +335,7 @@ def _emit_products(w: _W, prog: Program):
         else:
             w(f"const R b = {parent_var} * C[{comp}];")
         w(f"e = fma(xi[{a}], double(b), e);")
-        w(f"if (Bo) Bo[{a} * ldb] = double(b);")
+        w(f"if constexpr (WB) Bo[{a} * ldb] = double(b);")
         w(f"bb{a} = R(xi[{a}]);")
         if children[a]:
             w(f"const R p{a} = b;")
@@ -393,11 +394,14 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     w(f"static constexpr int TRIPLES = {prog.triple_count()};")
     w("static constexpr int GROUP_LO[NGROUP] = {" + ", ".join(str(g[0]) for g in groups) + "};")
     w("static constexpr int GROUP_HI[NGROUP] = {" + ", ".join(str(g[1]) for g in groups) + "};")
+    w("// flat moment layout: (mu, a, b, c) of component e")
+    w("static constexpr int ENTRIES[NMOM][4] = {" + ", ".join("{%d, %d, %d, %d}" % it for it in prog.layout.items) + "};")
     _emit_pair_functions(w, prog, groups)
     _emit_components_forward(w, prog)
     _emit_components_reverse(w, prog, groups)
     _emit_products(w, prog)
     _emit_dispatchers(w, len(groups))
+    emit_tangent_parts(w, prog, groups)
     w.pop()
     w("};")
     return w.text()
@@ -415,3 +419,300 @@ def write_level(level: int, out_dir: str, n_groups: int = 1) -> str:
         with open(path, "w") as fh:
             fh.write(text)
     return path
+
+
+# ======================================================================================
+# tangent (forward-mode) code for the parameter adjoint
+#
+# The parameter gradient needs, per atom, the directional derivative of every quantity
+# along the per-pair displacement change delta_ij = fbar_j - fbar_i:
+#   md   = sum_j d/dd [f_mu(r) mono_e(d)] . delta          (tangent of the moments)
+#   Cd, Bd                                                  (tangents of contractions/basis)
+#   Cbd, mbd                                                (tangents of the adjoints)
+# Each generated function mirrors its value counterpart and carries a tangent next to
+# every value (forward-over-reverse).
+
+
+def _emit_tangent_pair_functions(w: _W, prog: Program, groups):
+    items = prog.layout.items
+    for gi, (lo, hi) in enumerate(groups):
+        ents = list(range(lo, hi))
+        gnu = max(a + b + c for (_, a, b, c) in (items[e] for e in ents))
+        order = sorted({items[e][1:] for e in ents}, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1]))
+        # ---------------- tangent of the moments along delta
+        w("template <class R>")
+        w(f"static __device__ __forceinline__ void tan_moments_g{gi}(R* __restrict__ md, const R* __restrict__ f,")
+        w("    const R* __restrict__ fp, R x, R y, R z, R ex, R ey, R ez, R rdot) {")
+        w.push()
+        _emit_monomials_with_tangent(w, order)
+        by_mono = defaultdict(list)
+        for e in ents:
+            mu, a, b, c = items[e]
+            by_mono[(a, b, c)].append((e, mu))
+        for abc in order:
+            for e, mu in by_mono[abc]:
+                w(f"md[{e - lo}] = fma(f[{mu}], {_tmono_name(abc)}, fma(fp[{mu}] * rdot, {_mono_name(abc)}, md[{e - lo}]));")
+        w.pop()
+        w("}")
+        # ---------------- per-mu sums of the adjoint pair term
+        # S_mu = sum_e mb_e mono_e ;  A_mu = sum_e (mbd_e mono_e + mb_e dmono_e)
+        w("template <class R>")
+        w(f"static __device__ __forceinline__ void adj_pair_g{gi}(const R* __restrict__ mb, const R* __restrict__ mbd,")
+        w("    R x, R y, R z, R ex, R ey, R ez, R* __restrict__ S, R* __restrict__ A) {")
+        w.push()
+        _emit_monomials_with_tangent(w, order)
+        for abc in order:
+            for e, mu in by_mono[abc]:
+                w(f"S[{mu}] = fma(mb[{e - lo}], {_mono_name(abc)}, S[{mu}]);")
+                w(f"A[{mu}] = fma(mbd[{e - lo}], {_mono_name(abc)}, fma(mb[{e - lo}], {_tmono_name(abc)}, A[{mu}]));")
+        w.pop()
+        w("}")
+
+
+def _tmono_name(abc):
+    a, b, c = abc
+    return f"tmono_{a}_{b}_{c}"
+
+
+def _emit_monomials_with_tangent(w, order):
+    """mono = x^a y^b z^c and tmono = grad(mono) . (ex, ey, ez), built by one factor at a time."""
+    have = set()
+    need = set()
+    # close the set downwards along the construction chain
+    for abc in order:
+        a, b, c = abc
+        for k in range(c + 1):
+            need.add((a, b, k))
+        for k in range(b + 1):
+            need.add((a, k, 0))
+        for k in range(a + 1):
+            need.add((k, 0, 0))
+    for abc in sorted(need, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])):
+        a, b, c = abc
+        name, tname = _mono_name(abc), _tmono_name(abc)
+        if a + b + c == 0:
+            w(f"const R {name} = R(1);")
+            w(f"const R {tname} = R(0);")
+            have.add(abc)
+            continue
+        if c > 0:
+            low, var, ev = (a, b, c - 1), "z", "ez"
+        elif b > 0:
+            low, var, ev = (a, b - 1, 0), "y", "ey"
+        else:
+            low, var, ev = (a - 1, 0, 0), "x", "ex"
+        assert low in have
+        w(f"const R {name} = {_mono_name(low)} * {var};")
+        if low == (0, 0, 0):
+            w(f"const R {tname} = {ev};")
+        else:
+            w(f"const R {tname} = fma({_tmono_name(low)}, {var}, {_mono_name(low)} * {ev});")
+        have.add(abc)
+
+
+def _tref(r):
+    kind, k = r
+    if kind == "m":
+        return f"mde{k}"
+    if kind == "t":
+        return f"td{k}"
+    return f"Cd[{k}]"
+
+
+def _emit_block_forward_tangent(w: _W, blk, with_output=True):
+    for k in range(blk.n_temp):
+        w(f"R t{k} = R(0), td{k} = R(0);")
+    for (dst, x), lst in _group_ops(blk.ops).items():
+        if dst[0] == "c" and not with_output:
+            continue
+        if lst[0][0] is None:
+            w(f"{_ref(dst)} = {_ref(x)};")
+            w(f"{_tref(dst)} = {_tref(x)};")
+            continue
+        _emit_inner2(w, lst)
+        w(f"  {_tref(dst)} = fma({_tref(x)}, s, fma({_ref(x)}, sd, {_tref(dst)}));")
+        w(f"  {_ref(dst)} = fma({_ref(x)}, s, {_ref(dst)}); }}")
+
+
+def _emit_inner2(w, lst):
+    """s = sum w y and sd = sum w yd over a group."""
+    (y0, w0) = lst[0]
+    if w0 == 1:
+        w(f"{{ R s = {_ref(y0)}, sd = {_tref(y0)};")
+    else:
+        w(f"{{ R s = {_lit(w0)} * {_ref(y0)}, sd = {_lit(w0)} * {_tref(y0)};")
+    for y, wgt in lst[1:]:
+        if wgt == 1:
+            w(f"  s += {_ref(y)}; sd += {_tref(y)};")
+        else:
+            w(f"  s = fma({_lit(wgt)}, {_ref(y)}, s); sd = fma({_lit(wgt)}, {_tref(y)}, sd);")
+
+
+def _emit_components_forward_tangent(w: _W, prog: Program):
+    w("template <class R, class MA>")
+    w("static __device__ __forceinline__ void fwd_tan(const MA& M, const MA& Md, R* __restrict__ C, R* __restrict__ Cd) {")
+    w.push()
+    for blk in prog.blocks:
+        w(f"{{  // contraction {blk.q}")
+        w.push()
+        for e in blk.entries:
+            w(f"const R me{e} = M({e}), mde{e} = Md({e});")
+        w(f"C[{blk.q}] = R(0); Cd[{blk.q}] = R(0);")
+        _emit_block_forward_tangent(w, blk)
+        w.pop()
+        w("}")
+    w.pop()
+    w("}")
+
+
+def _adj2(ref, lo, hi):
+    """(adjoint, adjoint tangent) names of a reference inside a reverse-tangent block."""
+    kind, k = ref
+    if kind == "t":
+        return f"tb{k}", f"tbd{k}"
+    if kind == "m":
+        return (None, f"mbd[{k - lo}]") if lo <= k < hi else (None, None)
+    return "cb", "cbd"
+
+
+def _emit_block_reverse_tangent(w: _W, blk, lo, hi):
+    rev_ops = list(reversed(blk.ops))
+    seen_dst = []
+    by_dst = defaultdict(list)
+    for dst, x, y, wgt in rev_ops:
+        if dst not in by_dst:
+            seen_dst.append(dst)
+        by_dst[dst].append((x, y, wgt))
+    for dst in seen_dst:
+        lst = by_dst[dst]
+        db, dbd = _adj2(dst, lo, hi)
+        if lst[0][1] is None:
+            (x, _, _), = lst
+            xb, xbd = _adj2(x, lo, hi)
+            if xb:
+                w(f"{xb} += {db};")
+            if xbd:
+                w(f"{xbd} += {dbd};")
+            continue
+        xs, ys = {}, {}
+        for x, y, wgt in lst:
+            xs.setdefault(x, []).append((y, wgt))
+            ys.setdefault(y, []).append((x, wgt))
+        for x, l2 in xs.items():
+            xb, xbd = _adj2(x, lo, hi)
+            if not xb and not xbd:
+                continue
+            _emit_inner2(w, l2)
+            if xb:
+                w(f"  {xb} = fma({db}, s, {xb});")
+            w(f"  {xbd} = fma({dbd}, s, fma({db}, sd, {xbd})); }}")
+        for y, l2 in ys.items():
+            yb, ybd = _adj2(y, lo, hi)
+            if not ybd:
+                continue
+            _emit_inner2(w, l2)
+            w(f"  {ybd} = fma({dbd}, s, fma({db}, sd, {ybd})); }}")
+
+
+def _emit_components_reverse_tangent(w: _W, prog: Program, groups):
+    for gi, (lo, hi) in enumerate(groups):
+        w("template <class R, class MA>")
+        w(f"static __device__ __forceinline__ void rev_tan_g{gi}(const MA& M, const MA& Md, const R* __restrict__ Cb,")
+        w("    const R* __restrict__ Cbd, R* __restrict__ mbd) {")
+        w.push()
+        for blk in prog.blocks:
+            if not any(lo <= e < hi for e in blk.entries):
+                continue
+            w(f"{{  // contraction {blk.q}")
+            w.push()
+            w("MTP_BLOCK_FENCE();")
+            for e in blk.entries:
+                w(f"const R me{e} = M({e}), mde{e} = Md({e});")
+            w(f"const R cb = Cb[{blk.q}], cbd = Cbd[{blk.q}];")
+            _emit_block_forward_tangent(w, blk, with_output=False)
+            for k in range(blk.n_temp):
+                w(f"R tb{k} = R(0), tbd{k} = R(0);")
+            _emit_block_reverse_tangent(w, blk, lo, hi)
+            w.pop()
+            w("}")
+        w.pop()
+        w("}")
+
+
+def _emit_products_tangent(w: _W, prog: Program):
+    children = defaultdict(list)
+    roots = []
+    for a, (parent, comp) in enumerate(prog.trie):
+        if parent < 0:
+            roots.append(a)
+        else:
+            children[parent].append(a)
+    w("// Basis values and tangents; writes out[alpha * ld] = ebar B_alpha - dB_alpha, and the")
+    w("// adjoints Cb_q = dE_i/dC_q with their tangents Cbd_q.")
+    w("template <class R>")
+    w("static __device__ __forceinline__ void products_tan(const R* __restrict__ C, const R* __restrict__ Cd,")
+    w("    const double* __restrict__ xi, double ebar, R* __restrict__ Cb, R* __restrict__ Cbd,")
+    w("    double* __restrict__ out, long ld) {")
+    w.push()
+    for q in range(prog.n_comp):
+        w(f"Cb[{q}] = R(0); Cbd[{q}] = R(0);")
+
+    def node(a, pv, pdv):
+        parent, comp = prog.trie[a]
+        w(f"R bb{a}, bbd{a};")
+        w("{")
+        w.push()
+        if pv is None:
+            w(f"const R b = C[{comp}], bd = Cd[{comp}];")
+        else:
+            w(f"const R b = {pv} * C[{comp}];")
+            w(f"const R bd = fma({pdv}, C[{comp}], {pv} * Cd[{comp}]);")
+        w(f"out[{a} * ld] = fma(ebar, double(b), -double(bd));")
+        w(f"bb{a} = R(xi[{a}]); bbd{a} = R(0);")
+        if children[a]:
+            w(f"const R p{a} = b, pd{a} = bd;")
+            for ch in children[a]:
+                node(ch, f"p{a}", f"pd{a}")
+                _, cc = prog.trie[ch]
+                w(f"bbd{a} = fma(bbd{ch}, C[{cc}], fma(bb{ch}, Cd[{cc}], bbd{a}));")
+                w(f"bb{a} = fma(bb{ch}, C[{cc}], bb{a});")
+        w.pop()
+        w("}")
+        if pv is None:
+            w(f"Cb[{comp}] += bb{a}; Cbd[{comp}] += bbd{a};")
+        else:
+            w(f"Cbd[{comp}] = fma(bbd{a}, {pv}, fma(bb{a}, {pdv}, Cbd[{comp}]));")
+            w(f"Cb[{comp}] = fma(bb{a}, {pv}, Cb[{comp}]);")
+
+    for a in roots:
+        node(a, None, None)
+    w.pop()
+    w("}")
+
+
+def _emit_tangent_dispatchers(w: _W, n_groups: int):
+    sigs = (
+        ("tan_moments", "R* __restrict__ md, const R* __restrict__ f, const R* __restrict__ fp, R x, R y, R z, "
+                        "R ex, R ey, R ez, R rdot", "md, f, fp, x, y, z, ex, ey, ez, rdot", "class R", "<R>"),
+        ("adj_pair", "const R* __restrict__ mb, const R* __restrict__ mbd, R x, R y, R z, R ex, R ey, R ez, "
+                     "R* __restrict__ S, R* __restrict__ A", "mb, mbd, x, y, z, ex, ey, ez, S, A", "class R", "<R>"),
+        ("rev_tan", "const MA& M, const MA& Md, const R* __restrict__ Cb, const R* __restrict__ Cbd, "
+                    "R* __restrict__ mbd", "M, Md, Cb, Cbd, mbd", "class R, class MA", "<R, MA>"),
+    )
+    for name, params, args, tparams, targs in sigs:
+        w(f"template <int G, {tparams}>")
+        w(f"static __device__ __forceinline__ void {name}({params}) {{")
+        w.push()
+        for g in range(n_groups):
+            kw = "if constexpr" if g == 0 else "else if constexpr"
+            w(f"{kw} (G == {g}) {name}_g{g}{targs}({args});")
+        w.pop()
+        w("}")
+
+
+def emit_tangent_parts(w: _W, prog: Program, groups):
+    _emit_tangent_pair_functions(w, prog, groups)
+    _emit_components_forward_tangent(w, prog)
+    _emit_components_reverse_tangent(w, prog, groups)
+    _emit_products_tangent(w, prog)
+    _emit_tangent_dispatchers(w, len(groups))

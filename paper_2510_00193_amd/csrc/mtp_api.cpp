@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -348,7 +349,8 @@ SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist
 // Forward (moments, contractions, energies) and optionally the adjoint chain down to the
 // per-pair gradients g and per-workgroup virial partials, chunk by chunk.
 int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,
-                     bool backward, double* bvals, hipStream_t s) {
+                     bool backward, double* bvals, hipStream_t s,
+                     const std::function<void(int, int)>& after_forward) {
   const LevelOps& L = m->ops;
   const int n = sys->n_atoms;
   const int chunk = std::max(1, std::min(m->chunk, std::max(n, 1)));
@@ -380,6 +382,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
                  (const double*)m->shift.p, m->nsp, e_atom, cbar, bvals, s);
     }
+    if (after_forward) after_forward(i0, cn);
     if (backward) {
       for (int g = 0; g < L.ngroup; ++g) {
         ProfScope ps(&m->prof, P_PROG_REV, s);
@@ -413,7 +416,7 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
   }
   const bool backward = forces || virial;
   if (n > 0) {
-    if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s))) return rc;
+    if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s, nullptr))) return rc;
   }
   if (energy) {
     ProfScope ps(&m->prof, P_REDUCE, s);
@@ -429,6 +432,130 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
       launch_sum_virial((const double*)m->wpart.p, m->wblocks, virial, s);
     else
       HIP_TRY(hipMemsetAsync(virial, 0, 6 * sizeof(double), s));
+  }
+  HIP_TRY(hipGetLastError());
+  return MTP_OK;
+}
+
+extern "C" int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
+                         int mode, double* grade, double* grade_max, void* stream) {
+  int rc = check_system(m, sys);
+  if (rc) return rc;
+  if (!ainv || (sys->n_atoms > 0 && !grade) || !grade_max)
+    return mtp_fail(MTP_ERR_ARG, "null grade buffers or inverse active-set matrix");
+  if (mode != MTP_GRADE_FP64 && mode != MTP_GRADE_FP32SPLIT) return mtp_fail(MTP_ERR_ARG, "unknown grade mode");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = sys->n_atoms;
+  mtp_nlist use;
+  if ((rc = resolve_nlist(m, sys, nl, &use, s))) return rc;
+  const int na = m->ops.nalpha;
+  const long ld = std::max(1, std::min(m->chunk, std::max(n, 1)));
+  if ((rc = m->bvals.reserve((size_t)na * ld * sizeof(double))) ||
+      (rc = m->eatom.reserve((size_t)std::max(n, 1) * sizeof(double))))
+    return rc;
+  double* bv = (double*)m->bvals.p;
+  if (n > 0) {
+    rc = run_energy_chain(m, sys, use, (double*)m->eatom.p, false, bv, s, [&](int i0, int cn) {
+      ProfScope ps(&m->prof, P_GRADE, s);
+      launch_grade(bv, ld, cn, ainv, na, mode == MTP_GRADE_FP32SPLIT, grade + i0, s);
+    });
+    if (rc) return rc;
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_max(grade, n, grade_max, s);
+  } else {
+    HIP_TRY(hipMemsetAsync(grade_max, 0, sizeof(double), s));
+  }
+  HIP_TRY(hipGetLastError());
+  if (m->grade_select > 0.0 || m->grade_break > 0.0) {
+    double gm = 0.0;
+    HIP_TRY(hipMemcpyAsync(&gm, grade_max, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (m->grade_break > 0.0 && gm > m->grade_break) return MTP_GRADE_BREAK;
+    if (m->grade_select > 0.0 && gm > m->grade_select) return MTP_GRADE_SELECT;
+  }
+  return MTP_OK;
+}
+
+extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double ebar,
+                              const double* fbar, double* d_linear, double* d_radial, double* d_shift,
+                              void* stream) {
+  int rc = check_system(m, sys);
+  if (rc) return rc;
+  if ((sys->n_atoms > 0 && !fbar) || !d_linear || !d_radial || !d_shift)
+    return mtp_fail(MTP_ERR_ARG, "null fbar or gradient outputs");
+  if (!isfinite(ebar)) return mtp_fail(MTP_ERR_ARG, "non-finite ebar");
+  hipStream_t s = (hipStream_t)stream;
+  const LevelOps& L = m->ops;
+  const int n = sys->n_atoms;
+  const int na = L.nalpha;
+  const long K = m->nrad;  // nsp^2 * nmu * ncheb
+  if (n == 0) {
+    HIP_TRY(hipMemsetAsync(d_linear, 0, na * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(d_radial, 0, K * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(d_shift, 0, m->nsp * sizeof(double), s));
+    return MTP_OK;
+  }
+  mtp_nlist use;
+  if ((rc = resolve_nlist(m, sys, nl, &use, s))) return rc;
+  const int chunk = std::max(1, std::min(m->chunk, n));
+  const long ld = chunk;
+  const int nchunks = (n + chunk - 1) / chunk;
+  long nblk = 0;
+  for (int i0 = 0; i0 < n; i0 += chunk) nblk += (std::min(chunk, n - i0) + kLaneBlockHost - 1) / kLaneBlockHost;
+  const long nparts = nblk * L.ngroup;
+  if ((rc = m->mom.reserve((size_t)L.nmom * ld * 8)) || (rc = m->cbar.reserve((size_t)L.ncomp * ld * 8)) ||
+      (rc = m->mbar.reserve((size_t)L.nmom * ld * 8)) || (rc = m->mdot.reserve((size_t)L.nmom * ld * 8)) ||
+      (rc = m->cbard.reserve((size_t)L.ncomp * ld * 8)) || (rc = m->mbard.reserve((size_t)L.nmom * ld * 8)) ||
+      (rc = m->xout.reserve((size_t)na * ld * 8)) || (rc = m->eatom.reserve((size_t)n * 8)) ||
+      (rc = m->dxi_part.reserve((size_t)na * nchunks * 8)) || (rc = m->cpart.reserve((size_t)nparts * K * 8)))
+    return rc;
+  SysArgs a = make_sys_args(m, sys, use);
+  double *mom = (double*)m->mom.p, *cbar = (double*)m->cbar.p, *mbar = (double*)m->mbar.p;
+  double *mdot = (double*)m->mdot.p, *cbard = (double*)m->cbard.p, *mbard = (double*)m->mbard.p;
+  double *xout = (double*)m->xout.p, *dxp = (double*)m->dxi_part.p, *cpart = (double*)m->cpart.p;
+  long part = 0;
+  int c = 0;
+  for (int i0 = 0; i0 < n; i0 += chunk, ++c) {
+    const int cn = std::min(chunk, n - i0);
+    const long cblk = (cn + kLaneBlockHost - 1) / kLaneBlockHost;
+    for (int g = 0; g < L.ngroup; ++g) {
+      ProfScope ps(&m->prof, P_MOMENTS, s);
+      L.moments(g, a, i0, cn, mom, ld, s);
+    }
+    {
+      ProfScope ps(&m->prof, P_PROG_FWD, s);
+      L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p, (const double*)m->shift.p,
+                 m->nsp, (double*)m->eatom.p, cbar, nullptr, s);
+    }
+    for (int g = 0; g < L.ngroup; ++g) {
+      ProfScope ps(&m->prof, P_PROG_REV, s);
+      L.prog_rev(g, mom, ld, cn, cbar, mbar, s);
+    }
+    for (int g = 0; g < L.ngroup; ++g) {
+      ProfScope ps(&m->prof, P_TANGENT, s);
+      L.tan_moments(g, a, fbar, i0, cn, mdot, ld, s);
+    }
+    {
+      ProfScope ps(&m->prof, P_TANGENT, s);
+      L.tan_forward(mom, mdot, ld, cn, (const double*)m->linear.p, ebar, xout, cbard, s);
+    }
+    for (int g = 0; g < L.ngroup; ++g) {
+      ProfScope ps(&m->prof, P_TANGENT, s);
+      L.tan_reverse(g, mom, mdot, ld, cn, cbar, cbard, mbard, s);
+    }
+    for (int g = 0; g < L.ngroup; ++g) {
+      ProfScope ps(&m->prof, P_ADJ_PAIRS, s);
+      L.adj_pairs(g, a, fbar, i0, cn, mbar, mbard, ld, ebar, cpart + part * K, s);
+      part += cblk;
+    }
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_rowsum(xout, ld, 1, cn, na, dxp + c, nchunks, s);
+  }
+  {
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_rowsum(dxp, nchunks, 1, nchunks, na, d_linear, 1, s);
+    launch_rowsum(cpart, 1, K, part, (int)K, d_radial, 1, s);
+    launch_species_grad(sys->species, n, m->nsp, ebar, d_shift, s);
   }
   HIP_TRY(hipGetLastError());
   return MTP_OK;

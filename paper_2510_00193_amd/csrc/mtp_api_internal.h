@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -56,6 +57,7 @@ struct mtp_model {
   DevBuf radial, linear, shift;                        // coefficients (device)
   DevBuf nl_off, nl_j, nl_shift, nl_rev;               // internally built neighbour list
   DevBuf mom, cbar, mbar, bvals, g, eatom, wpart;      // per-chunk / per-pair workspace
+  DevBuf mdot, cbard, mbard, xout, dxi_part, cpart;   // parameter-adjoint workspace
   DevBuf scratch;
   long wblocks = 0;
   mtp::NbrWork* nbr = nullptr;
@@ -67,4 +69,5 @@ int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_
                   hipStream_t s);
 mtp::SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist& nl);
 int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,
-                     bool backward, double* bvals, hipStream_t s);
+                     bool backward, double* bvals, hipStream_t s,
+                     const std::function<void(int, int)>& after_forward);

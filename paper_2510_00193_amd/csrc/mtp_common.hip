@@ -46,7 +46,42 @@ __global__ __launch_bounds__(kSumThreads) void k_sum(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = s;
 }
 
+// out[r * os] = sum_{k < n} x[r * rs + k * es] for each row r (one workgroup per row, fixed order)
+__global__ __launch_bounds__(kNT) void k_rowsum(const double* __restrict__ x, long rs, long es, long n,
+                                                double* __restrict__ out, long os) {
+  __shared__ double sh[kNT];
+  const double* row = x + (long)blockIdx.x * rs;
+  double acc = 0.0;
+  for (long k = threadIdx.x; k < n; k += kNT) acc += row[k * es];
+  const double v = block_sum<kNT>(acc, sh);
+  if (threadIdx.x == 0) out[(long)blockIdx.x * os] = v;
+}
+
+// d(ebar E + fbar.F)/ds_t = ebar * (number of atoms of species t); integer counts are exact
+__global__ __launch_bounds__(kNT) void k_species_grad(const int* __restrict__ species, int n, int nsp,
+                                                      double ebar, double* __restrict__ out) {
+  __shared__ int cnt[16];
+  if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kNT) {
+    const int z = species[i];
+    if (z >= 0 && z < nsp) atomicAdd(&cnt[z], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < nsp) out[threadIdx.x] = ebar * (double)cnt[threadIdx.x];
+}
+
 }  // namespace
+
+void launch_rowsum(const double* x, long rs, long es, long n, int rows, double* out, long os,
+                   hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(kNT), 0, s, x, rs, es, n, out, os);
+}
+
+void launch_species_grad(const int* species, int n, int nsp, double ebar, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_species_grad, dim3(1), dim3(kNT), 0, s, species, n, nsp, ebar, out);
+}
 
 void launch_gather_forces(const int* off, const int* rev, const double* g, int n, long long npairs,
                           double* forces, hipStream_t s) {

@@ -3,6 +3,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Compiler-only memory fence placed between the contraction blocks of the generated
+// programs: it keeps the moment loads of a block from being hoisted above earlier blocks,
+// which would otherwise make every moment live at once and spill registers.
+#define MTP_BLOCK_FENCE() __builtin_amdgcn_sched_barrier(0)
+
 namespace mtp {
 
 constexpr int kMaxCheb = 16;

@@ -33,6 +33,15 @@ struct LevelOps {
                    hipStream_t s);
   void (*backward)(int grp, const SysArgs& a, int i0, int n, const double* mb, long ld, double* g,
                    int acc, double* wpart, hipStream_t s);
+  // parameter adjoint
+  void (*tan_moments)(int grp, const SysArgs& a, const double* fbar, int i0, int n, double* md,
+                      long ld, hipStream_t s);
+  void (*tan_forward)(const double* m, const double* md, long ld, int n, const double* xi,
+                      double ebar, double* out, double* cbard, hipStream_t s);
+  void (*tan_reverse)(int grp, const double* m, const double* md, long ld, int n, const double* cb,
+                      const double* cbd, double* mbd, hipStream_t s);
+  void (*adj_pairs)(int grp, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
+                    const double* mbd, long ld, double ebar, double* cpart, hipStream_t s);
 };
 
 // neighbour list (mtp_nbr.hip)
@@ -61,5 +70,15 @@ void launch_gather_forces(const int* off, const int* rev, const double* g, int n
                           double* forces, hipStream_t s);
 void launch_sum(const double* x, long n, long stride, double* out, hipStream_t s);
 void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream_t s);
+
+// out[r * os] = sum_{k < n} x[r * rs + k * es], r < rows (deterministic)
+void launch_rowsum(const double* x, long rs, long es, long n, int rows, double* out, long os,
+                   hipStream_t s);
+void launch_species_grad(const int* species, int n, int nsp, double ebar, double* out, hipStream_t s);
+
+// grade (mtp_grade.hip)
+void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,
+                  double* grade, hipStream_t s);
+void launch_max(const double* x, long n, double* out, hipStream_t s);
 
 }  // namespace mtp

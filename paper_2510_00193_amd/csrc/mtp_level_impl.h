@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const double* __rest
   double C[L::NCOMP];
   L::template fwd<double>(M, C);
   double Cb[L::NCOMP];
-  const double e = L::template products<double>(C, xi, Cb, bout ? bout + li : nullptr, ld);
+  const double e = bout ? L::template products<true, double>(C, xi, Cb, bout + li, ld)
+                        : L::template products<false, double>(C, xi, Cb, nullptr, ld);
   e_atom[i0 + li] = e + shift[clamp_species(species[i0 + li], nsp)];
 #pragma unroll
   for (int q = 0; q < L::NCOMP; ++q) cbar[(long)q * ld + li] = Cb[q];
@@ -180,6 +181,186 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
   }
 }
 
+// ---------------------------------------------------------------------------- parameter adjoint
+// Tangent of the moments along delta_ij = fbar_j - fbar_i (the direction in which the
+// force-weighted loss term differentiates the energy).
+template <class L, int G>
+__global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const double* __restrict__ fbar,
+                                                            int i0, int n, double* __restrict__ mdot,
+                                                            long ld) {
+  __shared__ double csh[kMaxRadial];
+  stage_radial(a, csh);
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  const int i = i0 + li;
+  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  double md[NG];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) md[e] = 0.0;
+  const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
+  const double fix = fbar[3 * i], fiy = fbar[3 * i + 1], fiz = fbar[3 * i + 2];
+  const int zi = clamp_species(a.species[i], a.nsp);
+  for (int p = a.off[i]; p < a.off[i + 1]; ++p) {
+    const int j = a.nj[p];
+    int n1, n2, n3;
+    unpack_shift(a.shift[p], n1, n2, n3);
+    double dx, dy, dz;
+    pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2, n3,
+                      a.H, dx, dy, dz);
+    const double r = sqrt(dist2_exact(dx, dy, dz));
+    const int zj = clamp_species(a.species[j], a.nsp);
+    double f[L::NMU], fp[L::NMU];
+    radial<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb,
+                           a.ncheb, f, fp);
+    const double ex = fbar[3 * j] - fix, ey = fbar[3 * j + 1] - fiy, ez = fbar[3 * j + 2] - fiz;
+    const double rdot = (dx * ex + dy * ey + dz * ez) / r;
+    L::template tan_moments<G>(md, f, fp, dx, dy, dz, ex, ey, ez, rdot);
+  }
+#pragma unroll
+  for (int e = 0; e < NG; ++e) mdot[(long)(LO + e) * ld + li] = md[e];
+}
+
+// Tangents of contractions and basis: out[alpha] = ebar B_alpha - dB_alpha, and dCbar.
+template <class L>
+__global__ __launch_bounds__(kLaneBlock) void k_tan_forward(const double* __restrict__ mom,
+                                                            const double* __restrict__ mdot, long ld,
+                                                            int n, const double* __restrict__ xi,
+                                                            double ebar, double* __restrict__ out,
+                                                            double* __restrict__ cbard) {
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  GlobalMoments<double> M{mom + li, ld}, Md{mdot + li, ld};
+  double C[L::NCOMP], Cd[L::NCOMP];
+  L::template fwd_tan<double>(M, Md, C, Cd);
+  double Cb[L::NCOMP], Cbd[L::NCOMP];
+  L::template products_tan<double>(C, Cd, xi, ebar, Cb, Cbd, out + li, ld);
+#pragma unroll
+  for (int q = 0; q < L::NCOMP; ++q) cbard[(long)q * ld + li] = Cbd[q];
+}
+
+// Tangent of the moment adjoint: mbd = d(mbar) along the moment tangent.
+template <class L, int G>
+__global__ __launch_bounds__(kLaneBlock) void k_tan_reverse(const double* __restrict__ mom,
+                                                            const double* __restrict__ mdot, long ld,
+                                                            int n, const double* __restrict__ cbar,
+                                                            const double* __restrict__ cbard,
+                                                            double* __restrict__ mbard) {
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  GlobalMoments<double> M{mom + li, ld}, Md{mdot + li, ld};
+  double Cb[L::NCOMP], Cbd[L::NCOMP];
+#pragma unroll
+  for (int q = 0; q < L::NCOMP; ++q) {
+    Cb[q] = cbar[(long)q * ld + li];
+    Cbd[q] = cbard[(long)q * ld + li];
+  }
+  double mbd[NG];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) mbd[e] = 0.0;
+  L::template rev_tan<G>(M, Md, Cb, Cbd, mbd);
+#pragma unroll
+  for (int e = 0; e < NG; ++e) mbard[(long)(LO + e) * ld + li] = mbd[e];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  return v;
+}
+
+// Radial-coefficient gradient: per pair (i, j) with species (s, t),
+//   dc[s][t][mu][b] += Q_b (ebar S_mu - A_mu) - Q'_b (rhat . delta) S_mu,
+// accumulated per lane for one neighbour species at a time and summed over the wave with a
+// fixed butterfly; one partial per (workgroup, s, t) lands in cpart.
+template <class L, int G>
+__global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const double* __restrict__ fbar,
+                                                          int i0, int n,
+                                                          const double* __restrict__ mbar,
+                                                          const double* __restrict__ mbard, long ld,
+                                                          double ebar, double* __restrict__ cpart) {
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  constexpr int NMU = L::NMU;
+  const int nq = a.ncheb;
+  const bool live = li < n;
+  const int i = i0 + (live ? li : 0);
+  double mb[NG], mbd[NG];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) {
+    mb[e] = live ? mbar[(long)(LO + e) * ld + li] : 0.0;
+    mbd[e] = live ? mbard[(long)(LO + e) * ld + li] : 0.0;
+  }
+  const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
+  const double fix = fbar[3 * i], fiy = fbar[3 * i + 1], fiz = fbar[3 * i + 2];
+  const int zi = clamp_species(a.species[i], a.nsp);
+  const int p0 = live ? a.off[i] : 0, p1 = live ? a.off[i + 1] : 0;
+  for (int t = 0; t < a.nsp; ++t) {
+    double acc[NMU * kMaxCheb];
+#pragma unroll
+    for (int k = 0; k < NMU * kMaxCheb; ++k) acc[k] = 0.0;
+    for (int p = p0; p < p1; ++p) {
+      const int j = a.nj[p];
+      if (clamp_species(a.species[j], a.nsp) != t) continue;
+      int n1, n2, n3;
+      unpack_shift(a.shift[p], n1, n2, n3);
+      double dx, dy, dz;
+      pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2,
+                        n3, a.H, dx, dy, dz);
+      const double r = sqrt(dist2_exact(dx, dy, dz));
+      const double ex = fbar[3 * j] - fix, ey = fbar[3 * j + 1] - fiy, ez = fbar[3 * j + 2] - fiz;
+      const double rdot = (dx * ex + dy * ey + dz * ez) / r;
+      double S[NMU], A[NMU];
+#pragma unroll
+      for (int mu = 0; mu < NMU; ++mu) S[mu] = A[mu] = 0.0;
+      L::template adj_pair<G>(mb, mbd, dx, dy, dz, ex, ey, ez, S, A);
+      double X[NMU], Y[NMU];
+#pragma unroll
+      for (int mu = 0; mu < NMU; ++mu) {
+        X[mu] = fma(ebar, S[mu], -A[mu]);
+        Y[mu] = -rdot * S[mu];
+      }
+      // Q_b = T_b(u) w^2, Q'_b = sa T'_b(u) w^2 - 2 T_b(u) w
+      const double u = fma(a.sa, r, a.sb), w = a.rcut - r, w2 = w * w;
+      double t2 = 1.0, t1 = u, d2 = 0.0, d1 = 1.0;
+#pragma unroll
+      for (int bq = 0; bq < kMaxCheb; ++bq) {
+        if (bq >= nq) break;
+        double T, D;
+        if (bq == 0) {
+          T = 1.0;
+          D = 0.0;
+        } else if (bq == 1) {
+          T = u;
+          D = 1.0;
+        } else {
+          T = fma(2.0 * u, t1, -t2);
+          D = fma(2.0 * u, d1, fma(2.0, t1, -d2));
+          t2 = t1;
+          t1 = T;
+          d2 = d1;
+          d1 = D;
+        }
+        const double q = T * w2, qp = fma(a.sa * w2, D, -2.0 * w * T);
+#pragma unroll
+        for (int mu = 0; mu < NMU; ++mu) acc[mu * kMaxCheb + bq] = fma(q, X[mu], fma(qp, Y[mu], acc[mu * kMaxCheb + bq]));
+      }
+    }
+    for (int sp = 0; sp < a.nsp; ++sp) {
+      for (int mu = 0; mu < NMU; ++mu)
+        for (int bq = 0; bq < nq; ++bq) {
+          const double v = wave_sum((live && zi == sp) ? acc[mu * kMaxCheb + bq] : 0.0);
+          if (threadIdx.x == 0)
+            cpart[(long)b * a.nsp * a.nsp * NMU * nq + ((sp * a.nsp + t) * NMU + mu) * nq + bq] = v;
+        }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------- launchers
 template <class L, int G>
 void launch_moments_g(const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s) {
@@ -238,6 +419,59 @@ struct LevelImpl {
     dispatch_backward<L>(grp, a, i0, n, mb, ld, gout, acc, wpart, s,
                          std::make_index_sequence<L::NGROUP>{});
   }
+  template <int G>
+  static void tan_moments_g(const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
+                            hipStream_t s) {
+    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    hipLaunchKernelGGL((k_tan_moments<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, md, ld);
+  }
+  template <size_t... Gs>
+  static void tan_moments_d(int g, const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
+                            hipStream_t s, std::index_sequence<Gs...>) {
+    ((g == (int)Gs ? tan_moments_g<(int)Gs>(a, fbar, i0, n, md, ld, s) : void()), ...);
+  }
+  static void tan_moments(int g, const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
+                          hipStream_t s) {
+    tan_moments_d(g, a, fbar, i0, n, md, ld, s, std::make_index_sequence<L::NGROUP>{});
+  }
+  static void tan_forward(const double* m, const double* md, long ld, int n, const double* xi, double ebar,
+                          double* out, double* cbard, hipStream_t s) {
+    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    hipLaunchKernelGGL((k_tan_forward<L>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, n, xi, ebar, out,
+                       cbard);
+  }
+  template <int G>
+  static void tan_reverse_g(const double* m, const double* md, long ld, int n, const double* cb,
+                            const double* cbd, double* mbd, hipStream_t s) {
+    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    hipLaunchKernelGGL((k_tan_reverse<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, n, cb, cbd, mbd);
+  }
+  template <size_t... Gs>
+  static void tan_reverse_d(int g, const double* m, const double* md, long ld, int n, const double* cb,
+                            const double* cbd, double* mbd, hipStream_t s, std::index_sequence<Gs...>) {
+    ((g == (int)Gs ? tan_reverse_g<(int)Gs>(m, md, ld, n, cb, cbd, mbd, s) : void()), ...);
+  }
+  static void tan_reverse(int g, const double* m, const double* md, long ld, int n, const double* cb,
+                          const double* cbd, double* mbd, hipStream_t s) {
+    tan_reverse_d(g, m, md, ld, n, cb, cbd, mbd, s, std::make_index_sequence<L::NGROUP>{});
+  }
+  template <int G>
+  static void adj_pairs_g(const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
+                          const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
+    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    hipLaunchKernelGGL((k_adj_pairs<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+                       ebar, cpart);
+  }
+  template <size_t... Gs>
+  static void adj_pairs_d(int g, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
+                          const double* mbd, long ld, double ebar, double* cpart, hipStream_t s,
+                          std::index_sequence<Gs...>) {
+    ((g == (int)Gs ? adj_pairs_g<(int)Gs>(a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s) : void()), ...);
+  }
+  static void adj_pairs(int g, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
+                        const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
+    adj_pairs_d(g, a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s, std::make_index_sequence<L::NGROUP>{});
+  }
   static LevelOps ops() {
     LevelOps o{};
     o.level = L::LEVEL;
@@ -252,6 +486,10 @@ struct LevelImpl {
     o.prog_fwd = &prog_fwd;
     o.prog_rev = &prog_rev;
     o.backward = &backward;
+    o.tan_moments = &tan_moments;
+    o.tan_forward = &tan_forward;
+    o.tan_reverse = &tan_reverse;
+    o.adj_pairs = &adj_pairs;
     return o;
   }
 };

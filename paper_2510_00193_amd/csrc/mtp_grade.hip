@@ -4,10 +4,12 @@
 //
 // One wave owns a tile of 16 atoms and sweeps the columns of Ainv in blocks of 8 MFMA tiles
 // (128 columns).  V_MFMA_F64_16X16X4F64 operand layout (wave64): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16], r = 0..3.
-// The FP32-split variant splits both operands into binary32 hi + lo parts, forms
-// hi*hi + hi*lo + lo*hi with V_MFMA_F32_16X16X4F32 (same layout) and adds every K=4 partial
-// into binary64 accumulators.
+// A[l % 16][l / 16] and B[l / 16][l % 16]; its accumulator register r holds
+// D[4 r + l / 16][l % 16], r = 0..3.  The FP32-split variant splits both operands into
+// binary32 hi + lo parts, forms hi*hi + hi*lo + lo*hi with V_MFMA_F32_16X16X4F32 (same input
+// layout, but register r holds D[4 (l / 16) + r][l % 16]) and adds every K=4 partial into
+// binary64 accumulators.  Both output layouts are checked on the device by the grade parity
+// tests.
 #include <hip/hip_runtime.h>
 
 #include "mtp_device.h"
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict_
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const double m = max16(rmax[r]);
-    const int out = i0 + 4 * kq + r;
+    const int out = SPLIT ? i0 + 4 * kq + r : i0 + 4 * r + kq;
     if (row == 0 && out < n) grade[out] = m;
   }
 }

@@ -22,6 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 
 # level -> number of moment-entry groups (register budget of the lane-per-atom kernels)
 LEVELS = {2: 1, 4: 1, 6: 1, 8: 1, 10: 1, 12: 1, 14: 1, 16: 1, 18: 2, 20: 3}
+# levels that also get the binary32-moment chain
+FP32_LEVELS = {2, 4, 6, 8, 10, 12, 14, 16}
 DEFAULT_LEVELS = (2, 4, 6, 8, 10, 12, 14, 16, 20)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -51,7 +53,8 @@ def generate(levels):
         write_level(lv, GEN, LEVELS[lv])
         _write_if_changed(os.path.join(GEN, f"mtp_L{lv}.hip"),
                           f'// Generated: kernels of level {lv}.\n#include "mtp_device.h"\n#include "gen/mtp_L{lv}.inc"\n'
-                          f'#include "mtp_level_impl.h"\nMTP_DEFINE_LEVEL(Lv{lv}, {lv})\n')
+                          f'#include "mtp_level_impl.h"\n'
+                          f'MTP_DEFINE_LEVEL(Lv{lv}, {lv}, {"true" if lv in FP32_LEVELS else "false"})\n')
     _write_if_changed(os.path.join(GEN, "levels.inc"),
                       "".join(f"MTP_LEVEL({lv})\n" for lv in levels))
 

@@ -188,6 +188,8 @@ int mtp_create(const mtp_params* p, mtp_model** out) {
   if (p->precision != MTP_FP64 && p->precision != MTP_FP32_MOMENTS)
     return mtp_fail(MTP_ERR_ARG, "unknown precision");
   if (p->chunk_atoms < 0) return mtp_fail(MTP_ERR_ARG, "chunk_atoms < 0");
+  if (p->precision == MTP_FP32_MOMENTS && !ops.chain[1].moments)
+    return mtp_fail(MTP_ERR_LEVEL, "the binary32 form is not compiled for level " + std::to_string(p->level));
   const long nrad = (long)p->n_species * p->n_species * ops.nmu * p->n_cheb;
   if (nrad > kMaxRadial) return mtp_fail(MTP_ERR_ARG, "radial table too large");
   mtp_model* m = new mtp_model();
@@ -352,6 +354,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
                      bool backward, double* bvals, hipStream_t s,
                      const std::function<void(int, int)>& after_forward) {
   const LevelOps& L = m->ops;
+  const ChainOps& K = L.chain[m->precision == MTP_FP32_MOMENTS ? 1 : 0];
   const int n = sys->n_atoms;
   const int chunk = std::max(1, std::min(m->chunk, std::max(n, 1)));
   const long ld = chunk;
@@ -367,30 +370,30 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       return rc;
   }
   SysArgs a = make_sys_args(m, sys, nl);
-  double* mom = (double*)m->mom.p;
-  double* cbar = (double*)m->cbar.p;
-  double* mbar = (double*)m->mbar.p;
+  void* mom = m->mom.p;
+  void* cbar = m->cbar.p;
+  void* mbar = m->mbar.p;
   long blk = 0;
   for (int i0 = 0; i0 < n; i0 += chunk) {
     const int cn = std::min(chunk, n - i0);
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_MOMENTS, s);
-      L.moments(g, a, i0, cn, mom, ld, s);
+      K.moments(g, a, i0, cn, mom, ld, s);
     }
     {
       ProfScope ps(&m->prof, P_PROG_FWD, s);
-      L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
+      K.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
                  (const double*)m->shift.p, m->nsp, e_atom, cbar, bvals, s);
     }
     if (after_forward) after_forward(i0, cn);
     if (backward) {
       for (int g = 0; g < L.ngroup; ++g) {
         ProfScope ps(&m->prof, P_PROG_REV, s);
-        L.prog_rev(g, mom, ld, cn, cbar, mbar, s);
+        K.prog_rev(g, mom, ld, cn, cbar, mbar, s);
       }
       for (int g = 0; g < L.ngroup; ++g) {
         ProfScope ps(&m->prof, P_BACKWARD, s);
-        L.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, s);
+        K.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, s);
       }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
     }
@@ -520,16 +523,16 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
     const long cblk = (cn + kLaneBlockHost - 1) / kLaneBlockHost;
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_MOMENTS, s);
-      L.moments(g, a, i0, cn, mom, ld, s);
+      L.chain[0].moments(g, a, i0, cn, mom, ld, s);
     }
     {
       ProfScope ps(&m->prof, P_PROG_FWD, s);
-      L.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p, (const double*)m->shift.p,
-                 m->nsp, (double*)m->eatom.p, cbar, nullptr, s);
+      L.chain[0].prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
+                          (const double*)m->shift.p, m->nsp, (double*)m->eatom.p, cbar, nullptr, s);
     }
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_PROG_REV, s);
-      L.prog_rev(g, mom, ld, cn, cbar, mbar, s);
+      L.chain[0].prog_rev(g, mom, ld, cn, cbar, mbar, s);
     }
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_TANGENT, s);

@@ -22,17 +22,22 @@ struct SysArgs {
   int nsp, nmu, ncheb;
 };
 
+// Energy/force chain of one level in one arithmetic type (per-atom buffers m, cbar, mbar are
+// arrays of that type; energies, pair gradients and virial partials stay binary64).
+struct ChainOps {
+  void (*moments)(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s);
+  void (*prog_fwd)(const void* m, long ld, int i0, int n, const int* species, const double* xi,
+                   const double* shift, int nsp, double* e_atom, void* cbar, double* bout,
+                   hipStream_t s);
+  void (*prog_rev)(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s);
+  void (*backward)(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
+                   int acc, double* wpart, hipStream_t s);
+};
+
 // Launchers of one compiled level (filled in by the level's translation unit).
 struct LevelOps {
   int level, nmom, ncomp, nalpha, nmu, maxnu, ngroup, triples;
-  void (*moments)(int g, const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s);
-  void (*prog_fwd)(const double* m, long ld, int i0, int n, const int* species, const double* xi,
-                   const double* shift, int nsp, double* e_atom, double* cbar, double* bout,
-                   hipStream_t s);
-  void (*prog_rev)(int g, const double* m, long ld, int n, const double* cb, double* mb,
-                   hipStream_t s);
-  void (*backward)(int grp, const SysArgs& a, int i0, int n, const double* mb, long ld, double* g,
-                   int acc, double* wpart, hipStream_t s);
+  ChainOps chain[2];  // [0] binary64, [1] binary32 moments (null when not compiled)
   // parameter adjoint
   void (*tan_moments)(int grp, const SysArgs& a, const double* fbar, int i0, int n, double* md,
                       long ld, hipStream_t s);

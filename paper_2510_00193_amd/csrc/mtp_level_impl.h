@@ -20,9 +20,9 @@ constexpr int kLaneBlock = 64;   // one wave per workgroup for the lane-per-atom
 // Accessor of a moment vector held in global memory in [entry][atom] layout.
 template <class R>
 struct GlobalMoments {
-  const double* __restrict__ p;
+  const R* __restrict__ p;
   long ld;
-  __device__ __forceinline__ R operator()(int e) const { return (R)p[(long)e * ld]; }
+  __device__ __forceinline__ R operator()(int e) const { return p[(long)e * ld]; }
 };
 
 template <class R>
@@ -31,27 +31,28 @@ struct RegMoments {
   __device__ __forceinline__ R operator()(int e) const { return m[e]; }
 };
 
-// radial coefficient table staged in LDS
-__device__ __forceinline__ void stage_radial(const SysArgs& a, double* sh) {
+// radial coefficient table staged in LDS (in the arithmetic type of the kernel)
+template <class R>
+__device__ __forceinline__ void stage_radial(const SysArgs& a, R* sh) {
   const int n = a.nsp * a.nsp * a.nmu * a.ncheb;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) sh[k] = a.radial[k];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) sh[k] = (R)a.radial[k];
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------- moments
-template <class L, int G>
+template <class L, int G, class R>
 __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
-                                                        double* __restrict__ mout, long ld) {
-  __shared__ double csh[kMaxRadial];
+                                                        R* __restrict__ mout, long ld) {
+  __shared__ R csh[kMaxRadial];
   stage_radial(a, csh);
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
   const int i = i0 + li;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
-  double m[NG];
+  R m[NG];
 #pragma unroll
-  for (int e = 0; e < NG; ++e) m[e] = 0.0;
+  for (int e = 0; e < NG; ++e) m[e] = R(0);
   const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
   const int p0 = a.off[i], p1 = a.off[i + 1];
@@ -64,54 +65,54 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
                       a.H, dx, dy, dz);
     const double r = sqrt(dist2_exact(dx, dy, dz));
     const int zj = clamp_species(a.species[j], a.nsp);
-    double f[L::NMU];
-    radial_values<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb,
-                                  a.ncheb, f);
-    L::template acc_moments<G>(m, f, dx, dy, dz);
+    R f[L::NMU];
+    radial_values<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut,
+                             csh + (zi * a.nsp + zj) * L::NMU * a.ncheb, a.ncheb, f);
+    L::template acc_moments<G>(m, f, (R)dx, (R)dy, (R)dz);
   }
 #pragma unroll
   for (int e = 0; e < NG; ++e) mout[(long)(LO + e) * ld + li] = m[e];
 }
 
 // ---------------------------------------------------------------------------- program forward
-template <class L>
-__global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const double* __restrict__ mom, long ld,
+template <class L, class R>
+__global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const R* __restrict__ mom, long ld,
                                                             int i0, int n, const int* __restrict__ species,
                                                             const double* __restrict__ xi,
                                                             const double* __restrict__ shift, int nsp,
                                                             double* __restrict__ e_atom,
-                                                            double* __restrict__ cbar,
+                                                            R* __restrict__ cbar,
                                                             double* __restrict__ bout) {
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  GlobalMoments<double> M{mom + li, ld};
-  double C[L::NCOMP];
-  L::template fwd<double>(M, C);
-  double Cb[L::NCOMP];
-  const double e = bout ? L::template products<true, double>(C, xi, Cb, bout + li, ld)
-                        : L::template products<false, double>(C, xi, Cb, nullptr, ld);
+  GlobalMoments<R> M{mom + li, ld};
+  R C[L::NCOMP];
+  L::template fwd<R>(M, C);
+  R Cb[L::NCOMP];
+  const double e = bout ? L::template products<true, R>(C, xi, Cb, bout + li, ld)
+                        : L::template products<false, R>(C, xi, Cb, nullptr, ld);
   e_atom[i0 + li] = e + shift[clamp_species(species[i0 + li], nsp)];
 #pragma unroll
   for (int q = 0; q < L::NCOMP; ++q) cbar[(long)q * ld + li] = Cb[q];
 }
 
 // ---------------------------------------------------------------------------- program reverse
-template <class L, int G>
-__global__ __launch_bounds__(kLaneBlock) void k_program_rev(const double* __restrict__ mom, long ld,
-                                                            int n, const double* __restrict__ cbar,
-                                                            double* __restrict__ mbar) {
+template <class L, int G, class R>
+__global__ __launch_bounds__(kLaneBlock) void k_program_rev(const R* __restrict__ mom, long ld,
+                                                            int n, const R* __restrict__ cbar,
+                                                            R* __restrict__ mbar) {
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
-  GlobalMoments<double> M{mom + li, ld};
-  double Cb[L::NCOMP];
+  GlobalMoments<R> M{mom + li, ld};
+  R Cb[L::NCOMP];
 #pragma unroll
   for (int q = 0; q < L::NCOMP; ++q) Cb[q] = cbar[(long)q * ld + li];
-  double mb[NG];
+  R mb[NG];
 #pragma unroll
-  for (int e = 0; e < NG; ++e) mb[e] = 0.0;
+  for (int e = 0; e < NG; ++e) mb[e] = R(0);
   L::template rev<G>(M, Cb, mb);
 #pragma unroll
   for (int e = 0; e < NG; ++e) mbar[(long)(LO + e) * ld + li] = mb[e];
@@ -119,12 +120,12 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_rev(const double* __rest
 
 // ---------------------------------------------------------------------------- backward pairs
 // g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials.
-template <class L, int G>
+template <class L, int G, class R>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
-                                                         const double* __restrict__ mbar, long ld,
+                                                         const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
                                                          double* __restrict__ wpart) {
-  __shared__ double csh[kMaxRadial];
+  __shared__ R csh[kMaxRadial];
   __shared__ double red[kLaneBlock];
   stage_radial(a, csh);
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
   double w[6] = {0, 0, 0, 0, 0, 0};
   if (li < n) {
     const int i = i0 + li;
-    double mb[NG];
+    R mb[NG];
 #pragma unroll
     for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li];
     const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
@@ -148,15 +149,15 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
                         n3, a.H, dx, dy, dz);
       const double r = sqrt(dist2_exact(dx, dy, dz));
       const int zj = clamp_species(a.species[j], a.nsp);
-      double f[L::NMU], fp[L::NMU];
-      radial<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb,
-                             a.ncheb, f, fp);
-      double gx = 0.0, gy = 0.0, gz = 0.0, u = 0.0;
-      L::template pair_grad<G>(mb, f, fp, dx, dy, dz, gx, gy, gz, u);
-      const double ur = u / r;
-      gx = fma(ur, dx, gx);
-      gy = fma(ur, dy, gy);
-      gz = fma(ur, dz, gz);
+      R f[L::NMU], fp[L::NMU];
+      radial<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut,
+                        csh + (zi * a.nsp + zj) * L::NMU * a.ncheb, a.ncheb, f, fp);
+      R rgx = R(0), rgy = R(0), rgz = R(0), ru = R(0);
+      L::template pair_grad<G>(mb, f, fp, (R)dx, (R)dy, (R)dz, rgx, rgy, rgz, ru);
+      const double ur = (double)ru / r;
+      const double gx = fma(ur, dx, (double)rgx);
+      const double gy = fma(ur, dy, (double)rgy);
+      const double gz = fma(ur, dz, (double)rgz);
       if (accumulate) {
         g[3L * p] += gx;
         g[3L * p + 1] += gy;
@@ -362,63 +363,68 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <class L, int G>
-void launch_moments_g(const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s) {
+template <class L, int G, class R>
+void launch_moments_g(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_moments<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, m, ld);
+  hipLaunchKernelGGL((k_moments<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
 }
-template <class L, int G>
-void launch_rev_g(const double* m, long ld, int n, const double* cb, double* mb, hipStream_t s) {
+template <class L, int G, class R>
+void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_program_rev<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, m, ld, n, cb, mb);
+  hipLaunchKernelGGL((k_program_rev<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, n,
+                     (const R*)cb, (R*)mb);
 }
-template <class L, int G>
-void launch_backward_g(const SysArgs& a, int i0, int n, const double* mb, long ld, double* g,
+template <class L, int G, class R>
+void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                        int acc, double* wpart, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_backward<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, mb, ld, g, acc,
-                     wpart);
+  hipLaunchKernelGGL((k_backward<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (const R*)mb,
+                     ld, g, acc, wpart);
 }
 
-template <class L, size_t... Gs>
-void dispatch_moments(int g, const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s,
+template <class L, class R, size_t... Gs>
+void dispatch_moments(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s,
                       std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_moments_g<L, (int)Gs>(a, i0, n, m, ld, s) : void()), ...);
+  ((g == (int)Gs ? launch_moments_g<L, (int)Gs, R>(a, i0, n, m, ld, s) : void()), ...);
 }
-template <class L, size_t... Gs>
-void dispatch_rev(int g, const double* m, long ld, int n, const double* cb, double* mb,
-                  hipStream_t s, std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_rev_g<L, (int)Gs>(m, ld, n, cb, mb, s) : void()), ...);
+template <class L, class R, size_t... Gs>
+void dispatch_rev(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s,
+                  std::index_sequence<Gs...>) {
+  ((g == (int)Gs ? launch_rev_g<L, (int)Gs, R>(m, ld, n, cb, mb, s) : void()), ...);
 }
-template <class L, size_t... Gs>
-void dispatch_backward(int g, const SysArgs& a, int i0, int n, const double* mb, long ld,
+template <class L, class R, size_t... Gs>
+void dispatch_backward(int g, const SysArgs& a, int i0, int n, const void* mb, long ld,
                        double* gout, int acc, double* wpart, hipStream_t s,
                        std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_backward_g<L, (int)Gs>(a, i0, n, mb, ld, gout, acc, wpart, s) : void()),
+  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R>(a, i0, n, mb, ld, gout, acc, wpart, s) : void()),
    ...);
 }
 
-template <class L>
-struct LevelImpl {
-  static void moments(int g, const SysArgs& a, int i0, int n, double* m, long ld, hipStream_t s) {
-    dispatch_moments<L>(g, a, i0, n, m, ld, s, std::make_index_sequence<L::NGROUP>{});
+template <class L, class R>
+struct EnergyChain {
+  static void moments(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
+    dispatch_moments<L, R>(g, a, i0, n, m, ld, s, std::make_index_sequence<L::NGROUP>{});
   }
-  static void prog_fwd(const double* m, long ld, int i0, int n, const int* species,
-                       const double* xi, const double* shift, int nsp, double* e_atom, double* cbar,
-                       double* bout, hipStream_t s) {
-    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-    hipLaunchKernelGGL((k_program_fwd<L>), dim3(nb), dim3(kLaneBlock), 0, s, m, ld, i0, n, species,
-                       xi, shift, nsp, e_atom, cbar, bout);
-  }
-  static void prog_rev(int g, const double* m, long ld, int n, const double* cb, double* mb,
+  static void prog_fwd(const void* m, long ld, int i0, int n, const int* species, const double* xi,
+                       const double* shift, int nsp, double* e_atom, void* cbar, double* bout,
                        hipStream_t s) {
-    dispatch_rev<L>(g, m, ld, n, cb, mb, s, std::make_index_sequence<L::NGROUP>{});
+    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    hipLaunchKernelGGL((k_program_fwd<L, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, i0, n,
+                       species, xi, shift, nsp, e_atom, (R*)cbar, bout);
   }
-  static void backward(int grp, const SysArgs& a, int i0, int n, const double* mb, long ld,
-                       double* gout, int acc, double* wpart, hipStream_t s) {
-    dispatch_backward<L>(grp, a, i0, n, mb, ld, gout, acc, wpart, s,
-                         std::make_index_sequence<L::NGROUP>{});
+  static void prog_rev(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s) {
+    dispatch_rev<L, R>(g, m, ld, n, cb, mb, s, std::make_index_sequence<L::NGROUP>{});
   }
+  static void backward(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* gout,
+                       int acc, double* wpart, hipStream_t s) {
+    dispatch_backward<L, R>(grp, a, i0, n, mb, ld, gout, acc, wpart, s,
+                            std::make_index_sequence<L::NGROUP>{});
+  }
+  static ChainOps ops() { return ChainOps{&moments, &prog_fwd, &prog_rev, &backward}; }
+};
+
+template <class L, bool WITH_FP32>
+struct LevelImpl {
   template <int G>
   static void tan_moments_g(const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
                             hipStream_t s) {
@@ -482,10 +488,8 @@ struct LevelImpl {
     o.maxnu = L::MAXNU;
     o.ngroup = L::NGROUP;
     o.triples = L::TRIPLES;
-    o.moments = &moments;
-    o.prog_fwd = &prog_fwd;
-    o.prog_rev = &prog_rev;
-    o.backward = &backward;
+    o.chain[0] = EnergyChain<L, double>::ops();
+    if constexpr (WITH_FP32) o.chain[1] = EnergyChain<L, float>::ops();
     o.tan_moments = &tan_moments;
     o.tan_forward = &tan_forward;
     o.tan_reverse = &tan_reverse;
@@ -496,7 +500,7 @@ struct LevelImpl {
 
 }  // namespace mtp
 
-#define MTP_DEFINE_LEVEL(LV, NUM)                                  \
-  namespace mtp {                                                  \
-  LevelOps level_ops_##NUM() { return LevelImpl<LV>::ops(); }      \
+#define MTP_DEFINE_LEVEL(LV, NUM, FP32)                                  \
+  namespace mtp {                                                        \
+  LevelOps level_ops_##NUM() { return LevelImpl<LV, FP32>::ops(); }      \
   }

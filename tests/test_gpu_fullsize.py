@@ -1,0 +1,83 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark times.
+
+The oracle computes sampled outputs one by one (neighbour rows, site energies, basis
+vectors and forces of a few atoms); properties that hold at any size are checked on the
+whole system.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from helpers import TOL_E, TOL_F, TOL_GRADE, rel_err
+from oracle import mtp as om
+from oracle import neighbors as onb
+
+pytestmark = pytest.mark.gpu
+
+
+def _load(k):
+    from paper_2510_00193_amd import Potential, level_info
+    info = level_info(wl.WORKLOADS[k]["level"])
+    w = wl.workload(k, info["n_alpha"], info["n_mu"])
+    (s,) = w["structures"]
+    return s, w, Potential.from_params(w["params"])
+
+
+def _sampled_checks(s, p, pot, atoms, label):
+    pos = torch.as_tensor(s.pos, device="cuda")
+    sp = torch.as_tensor(s.species, device="cuda")
+    print(f"[{label}] N={s.n_atoms}", flush=True)
+    nl = pot.neighbors(pos, sp, s.cell)
+    out = pot.compute(pos, sp, s.cell, nlist=nl, e_atom=True)
+    torch.cuda.synchronize()
+    off = nl.off.cpu().numpy()
+    j = nl.j.cpu().numpy()
+    sh = onb.unpack_shift(nl.shift.cpu().numpy())
+    rev = nl.rev.cpu().numpy()
+    # the whole list: mirrored pairs, sorted rows
+    assert np.array_equal(rev[rev], np.arange(len(rev)))
+    assert np.array_equal(j[rev], np.repeat(np.arange(s.n_atoms), np.diff(off)))
+    model = om.Model.from_params(p)
+    rows, e_ref, _ = om.sampled_site_values(model, s, atoms)
+    for a, (js, ns) in zip(atoms, rows):
+        np.testing.assert_array_equal(j[off[a]:off[a + 1]], js)
+        np.testing.assert_array_equal(sh[off[a]:off[a + 1]], ns)
+    e_gpu = out["e_atom"].cpu().numpy()
+    assert rel_err(e_gpu[atoms], e_ref) < TOL_E
+    f_ref = om.sampled_forces(model, s, atoms[:3])
+    f_gpu = out["forces"].cpu().numpy()
+    # forces relative to the largest force of the system
+    assert np.max(np.abs(f_gpu[atoms[:3]] - f_ref)) / np.abs(f_gpu).max() < TOL_F
+    assert np.abs(f_gpu.sum(axis=0)).max() <= 1e-9 * np.abs(f_gpu).max()
+    etot = float(out["energy"].cpu())
+    assert abs(etot - e_gpu.sum()) <= 1e-12 * np.abs(e_gpu).sum()
+    return pot, pos, sp, nl
+
+
+def test_workload2_sampled():
+    s, w, pot = _load(2)
+    rng = np.random.default_rng(22)
+    _sampled_checks(s, w["params"], pot, list(rng.choice(s.n_atoms, 6, replace=False)), "bcc-20^3-2sp-L16")
+
+
+def test_workload3_sampled():
+    s, w, pot = _load(3)
+    rng = np.random.default_rng(33)
+    atoms = [0, s.n_atoms - 1] + list(rng.choice(s.n_atoms, 4, replace=False))
+    _sampled_checks(s, w["params"], pot, atoms, "bcc-80^3-L16")
+
+
+def test_workload4_sampled_grade():
+    s, w, pot = _load(4)
+    rng = np.random.default_rng(44)
+    atoms = list(rng.choice(s.n_atoms, 6, replace=False))
+    pot, pos, sp, nl = _sampled_checks(s, w["params"], pot, atoms, "fcc-50x50x25-3sp-L16")
+    ainv = w["extra"]["active_set_inv"]
+    out = pot.grade(pos, sp, s.cell, torch.as_tensor(ainv, device="cuda"), nlist=nl)
+    torch.cuda.synchronize()
+    _, _, b_ref = om.sampled_site_values(om.Model.from_params(w["params"]), s, atoms)
+    g_ref = om.grade(b_ref, ainv)
+    g = out["grade"].cpu().numpy()
+    assert np.max(np.abs(g[atoms] - g_ref) / np.maximum(1.0, g_ref)) < TOL_GRADE
+    assert float(out["grade_max"].cpu()) == pytest.approx(g.max(), rel=0, abs=0)

@@ -153,6 +153,43 @@ int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, dou
                    const double* fbar, double* d_linear, double* d_radial, double* d_shift,
                    void* stream);
 
+/* ---- Batched training over many small configurations ------------------------------------
+ * Not in the paper, which evaluates one configuration per MD step; this is the batched form
+ * of the same path for fitting on a training set.  The batch always runs in binary64.
+ *
+ * mtp_batch_create: configurations c = 0..n_cfg-1 hold atoms atom_off[c] .. atom_off[c+1]-1
+ *   (host int array, atom_off[0] = 0, non-decreasing); pos (device [N][3]) and species
+ *   (device [N]) are referenced, not copied, and must stay valid for the batch's lifetime;
+ *   cells (host [n_cfg][9], rows = lattice vectors) are copied.  Builds every
+ *   configuration's canonical neighbour list once (synchronizes) and reserves all workspace.
+ * mtp_batch_run: energies [n_cfg], forces [N][3], virials [n_cfg][6] (device, any may be
+ *   NULL) of every configuration; with targets e_target [n_cfg] and f_target [N][3] also the
+ *   loss L = sum_c (E_c - E0_c)^2 + sum_i |F_i - F0_i|^2 (loss [1], may be NULL) and its
+ *   gradient d_linear [n_alpha], d_radial [n_sp^2 n_mu n_cheb], d_shift [n_sp] (device).
+ *   One launch per kernel type covers all configurations.  It allocates nothing and never
+ *   synchronizes; with use_graph != 0 the sequence is captured once into a hipGraph (per set
+ *   of output pointers) and replayed on an internal stream ordered after and before the
+ *   caller's stream.  Coefficient updates through mtp_set_params(on_device = 1) reach the
+ *   replays without re-capture.
+ * mtp_batch_tune: times the atom-to-lane schedules (natural order or sorted by neighbour
+ *   count; chunk sizes) on this batch and keeps the fastest; with cache_path (text file)
+ *   the pick is read back for the same level, species, basis size and size bucket.
+ *   choice (host [2], may be NULL) receives {sorted, chunk_atoms}.  Synchronizes.
+ * mtp_batch_schedule: sets a schedule explicitly (sorted 0/1, chunk_atoms 0 = all atoms).
+ * mtp_batch_neighbors: device pointers of the batch's CSR list (global atom indices). */
+typedef struct mtp_batch mtp_batch;
+int mtp_batch_create(mtp_model* m, int n_cfg, const int* atom_off, const double* pos, const int* species,
+                     const double* cells, mtp_batch** out, void* stream);
+int mtp_batch_run(mtp_batch* b, const double* e_target, const double* f_target, double* energy,
+                  double* forces, double* virial, double* loss, double* d_linear, double* d_radial,
+                  double* d_shift, int use_graph, void* stream);
+int mtp_batch_tune(mtp_batch* b, const char* cache_path, int* choice, void* stream);
+int mtp_batch_schedule(mtp_batch* b, int sorted, int chunk_atoms);
+int mtp_batch_sizes(const mtp_batch* b, int* n_atoms, long long* n_pairs, int* sorted, int* chunk_atoms);
+int mtp_batch_neighbors(const mtp_batch* b, const int** off, const int** j, const int** shift,
+                        const int** rev);
+void mtp_batch_destroy(mtp_batch* b);
+
 /* Per-kernel timing with HIP events recorded on the caller's stream around every launch of the
  * hot path (for benchmarks; off by default).  mtp_profile_read synchronizes the recorded
  * events, adds them to the totals, and reports kernel class k: its name (static string),

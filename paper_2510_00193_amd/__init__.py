@@ -5,4 +5,4 @@ adjoint to forces and virial, extrapolation grade, parameter gradients) runs
 in hand-written HIP kernels behind the C ABI declared in include/mtp.h.
 This package only builds the library and marshals arguments to it.
 """
-from .api import NeighborList, Potential, compiled_levels, level_info  # noqa: F401
+from .api import Batch, NeighborList, Potential, compiled_levels, level_info  # noqa: F401

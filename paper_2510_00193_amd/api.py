@@ -213,3 +213,90 @@ class Potential:
         check(self._lib.mtp_param_grad(self._h, ctypes.byref(sysc), nl, float(ebar), _ptr(fbar), _ptr(dl),
                                        _ptr(dr), _ptr(ds), _stream()))
         return dl, dr, ds
+
+
+class Batch:
+    """Many small periodic configurations evaluated together (training sets).
+
+    positions [N, 3] float64 and species [N] int32 live on the GPU and are referenced by the
+    library for the batch's lifetime (this object keeps them alive); atom_off [n_cfg + 1]
+    and cells [n_cfg, 3, 3] are host arrays.  The neighbour lists are built once here.
+    """
+
+    def __init__(self, pot: Potential, atom_off, pos, species, cells):
+        self._lib = pot._lib
+        self._pot = pot
+        self._h = None
+        n = int(pos.shape[0])
+        _dev(pos, torch.float64, (n, 3), "pos")
+        _dev(species, torch.int32, (n,), "species")
+        self.atom_off = np.ascontiguousarray(atom_off, dtype=np.int32)
+        self.cells = np.ascontiguousarray(cells, dtype=np.float64).reshape(-1, 9)
+        self.n_cfg = int(self.cells.shape[0])
+        if self.atom_off.shape != (self.n_cfg + 1,):
+            raise ValueError("atom_off must have n_cfg + 1 entries")
+        self.pos, self.species = pos, species
+        h = ctypes.c_void_p()
+        off_c = self.atom_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        check(self._lib.mtp_batch_create(pot._h, self.n_cfg, off_c, _ptr(pos), _ptr(species),
+                                         self.cells.ctypes.data_as(_lib.c_double_p), ctypes.byref(h), _stream()))
+        self._h = h
+        self.n_atoms = n
+        self.n_alpha, self.n_mu = pot.n_alpha, pot.n_mu
+
+    def close(self):
+        if self._h is not None:
+            self._lib.mtp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self):
+        n, p, so, ch = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
+        check(self._lib.mtp_batch_sizes(self._h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(so), ctypes.byref(ch)))
+        return {"n_atoms": n.value, "n_pairs": p.value, "sorted": so.value, "chunk_atoms": ch.value}
+
+    def schedule(self, sorted=False, chunk_atoms=0):
+        check(self._lib.mtp_batch_schedule(self._h, 1 if sorted else 0, int(chunk_atoms)))
+
+    def tune(self, cache_path=None):
+        choice = (ctypes.c_int * 2)()
+        path = cache_path.encode() if cache_path else None
+        check(self._lib.mtp_batch_tune(self._h, path, choice, _stream()))
+        return {"sorted": choice[0], "chunk_atoms": choice[1]}
+
+    def neighbors(self):
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        check(self._lib.mtp_batch_neighbors(self._h, *[ctypes.byref(x) for x in ptrs]))
+        return [p.value for p in ptrs]
+
+    def outputs(self, loss=True):
+        dev = self.pos.device
+        out = {"energy": torch.empty(self.n_cfg, dtype=torch.float64, device=dev),
+               "forces": torch.empty((self.n_atoms, 3), dtype=torch.float64, device=dev),
+               "virial": torch.empty((self.n_cfg, 6), dtype=torch.float64, device=dev)}
+        if loss:
+            p = self._pot
+            out.update({"loss": torch.empty(1, dtype=torch.float64, device=dev),
+                        "d_linear": torch.empty(p.n_alpha, dtype=torch.float64, device=dev),
+                        "d_radial": torch.empty((p.n_species, p.n_species, p.n_mu, p.n_cheb), dtype=torch.float64,
+                                                device=dev),
+                        "d_shift": torch.empty(p.n_species, dtype=torch.float64, device=dev)})
+        return out
+
+    def run(self, out, e_target=None, f_target=None, use_graph=False):
+        """Fill the preallocated dict from outputs(); with targets also the loss gradient."""
+        if (e_target is None) != (f_target is None):
+            raise ValueError("give both targets or neither")
+        if e_target is not None:
+            _dev(e_target, torch.float64, (self.n_cfg,), "e_target")
+            _dev(f_target, torch.float64, (self.n_atoms, 3), "f_target")
+        g = lambda k: _ptr(out[k]) if k in out else None  # noqa: E731
+        check(self._lib.mtp_batch_run(self._h, _ptr(e_target), _ptr(f_target), g("energy"), g("forces"),
+                                      g("virial"), g("loss"), g("d_linear"), g("d_radial"), g("d_shift"),
+                                      1 if use_graph else 0, _stream()))
+        return out

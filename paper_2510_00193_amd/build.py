@@ -69,7 +69,8 @@ def _compile(src, obj):
 
 
 def sources(levels):
-    out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_nbr.hip", "mtp_common.hip", "mtp_grade.hip")]
+    out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_batch.cpp", "mtp_nbr.hip", "mtp_common.hip",
+                                           "mtp_grade.hip")]
     out += [os.path.join(GEN, f"mtp_L{lv}.hip") for lv in levels]
     return out
 

@@ -339,6 +339,10 @@ SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist
   a.shift = nl.shift;
   a.radial = (const double*)m->radial.p;
   for (int k = 0; k < 9; ++k) a.H[k] = sys->cell[k];
+  a.cells = nullptr;
+  a.cfg = nullptr;
+  a.perm = nullptr;
+  a.ebar = nullptr;
   a.sa = 2.0 / (m->rcut - m->rmin);
   a.sb = -(m->rmin + m->rcut) / (m->rcut - m->rmin);
   a.rcut = m->rcut;
@@ -382,7 +386,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
     }
     {
       ProfScope ps(&m->prof, P_PROG_FWD, s);
-      K.prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
+      K.prog_fwd(mom, ld, i0, cn, nullptr, sys->species, (const double*)m->linear.p,
                  (const double*)m->shift.p, m->nsp, e_atom, cbar, bvals, s);
     }
     if (after_forward) after_forward(i0, cn);
@@ -393,7 +397,8 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       }
       for (int g = 0; g < L.ngroup; ++g) {
         ProfScope ps(&m->prof, P_BACKWARD, s);
-        K.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, s);
+        K.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, nullptr,
+                   s);
       }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
     }
@@ -527,7 +532,7 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
     }
     {
       ProfScope ps(&m->prof, P_PROG_FWD, s);
-      L.chain[0].prog_fwd(mom, ld, i0, cn, sys->species, (const double*)m->linear.p,
+      L.chain[0].prog_fwd(mom, ld, i0, cn, nullptr, sys->species, (const double*)m->linear.p,
                           (const double*)m->shift.p, m->nsp, (double*)m->eatom.p, cbar, nullptr, s);
     }
     for (int g = 0; g < L.ngroup; ++g) {
@@ -540,7 +545,7 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
     }
     {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_forward(mom, mdot, ld, cn, (const double*)m->linear.p, ebar, xout, cbard, s);
+      L.tan_forward(a, mom, mdot, ld, i0, cn, (const double*)m->linear.p, ebar, xout, cbard, s);
     }
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_TANGENT, s);

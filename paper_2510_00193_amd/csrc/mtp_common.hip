@@ -71,7 +71,76 @@ __global__ __launch_bounds__(kNT) void k_species_grad(const int* __restrict__ sp
   if (threadIdx.x < nsp) out[threadIdx.x] = ebar * (double)cnt[threadIdx.x];
 }
 
+// out[seg * os + comp] = sum over atoms i of segment seg of x[i * stride + comp]
+// (one workgroup per (segment, component), fixed order)
+__global__ __launch_bounds__(kNT) void k_segsum(const double* __restrict__ x, long stride,
+                                                const int* __restrict__ seg_off,
+                                                double* __restrict__ out, long os) {
+  __shared__ double sh[kNT];
+  const int seg = blockIdx.x, comp = blockIdx.y;
+  double acc = 0.0;
+  for (long i = seg_off[seg] + threadIdx.x; i < seg_off[seg + 1]; i += kNT) acc += x[i * stride + comp];
+  const double v = block_sum<kNT>(acc, sh);
+  if (threadIdx.x == 0) out[(long)seg * os + comp] = v;
+}
+
+// Loss (E_c - E0_c)^2 + sum_i |F_i - F0_i|^2 per configuration: cotangents and per-item parts.
+__global__ void k_loss_cfg(const double* __restrict__ e, const double* __restrict__ e0, int ncfg,
+                           double* __restrict__ ebar, double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncfg) return;
+  const double d = e[c] - e0[c];
+  ebar[c] = 2.0 * d;
+  part[c] = d * d;
+}
+__global__ void k_loss_atoms(const double* __restrict__ f, const double* __restrict__ f0, long n,
+                             double* __restrict__ fbar, double* __restrict__ part) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double d = f[3 * i + k] - f0[3 * i + k];
+    fbar[3 * i + k] = 2.0 * d;
+    acc = fma(d, d, acc);
+  }
+  part[i] = acc;
+}
+
+// ds_t = sum_i ebar_{cfg(i)} [z_i = t] (one workgroup per species, fixed order)
+__global__ __launch_bounds__(kNT) void k_species_grad_cfg(const int* __restrict__ species,
+                                                          const int* __restrict__ cfg,
+                                                          const double* __restrict__ ebar, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[kNT];
+  const int t = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kNT)
+    if (species[i] == t) acc += ebar[cfg[i]];
+  const double v = block_sum<kNT>(acc, sh);
+  if (threadIdx.x == 0) out[t] = v;
+}
+
 }  // namespace
+
+void launch_segsum(const double* x, long stride, const int* seg_off, int nseg, int ncomp, double* out,
+                   long os, hipStream_t s) {
+  if (nseg <= 0) return;
+  hipLaunchKernelGGL(k_segsum, dim3(nseg, ncomp), dim3(kNT), 0, s, x, stride, seg_off, out, os);
+}
+
+void launch_loss(const double* e, const double* e0, int ncfg, const double* f, const double* f0, long n,
+                 double* ebar, double* fbar, double* part_cfg, double* part_atoms, hipStream_t s) {
+  if (ncfg > 0) hipLaunchKernelGGL(k_loss_cfg, dim3((ncfg + kNT - 1) / kNT), dim3(kNT), 0, s, e, e0, ncfg, ebar,
+                                   part_cfg);
+  if (n > 0) hipLaunchKernelGGL(k_loss_atoms, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s, f, f0, n,
+                                fbar, part_atoms);
+}
+
+void launch_species_grad_cfg(const int* species, const int* cfg, const double* ebar, int n, int nsp,
+                             double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_species_grad_cfg, dim3(nsp), dim3(kNT), 0, s, species, cfg, ebar, n, out);
+}
 
 void launch_rowsum(const double* x, long rs, long es, long n, int rows, double* out, long os,
                    hipStream_t s) {

@@ -122,6 +122,19 @@ __device__ __forceinline__ void radial_values(R r, R sa, R sb, R rcut, const R* 
   for (int mu = 0; mu < NMU; ++mu) f[mu] = w2 * A[mu];
 }
 
+// Atom handled by sweep position k, and its cell (kernel-argument copy for one system, the
+// configuration's row of the cell table for batches).
+template <class A>
+__device__ __forceinline__ int atom_at(const A& a, int k) {
+  return a.perm ? a.perm[k] : k;
+}
+template <class A>
+__device__ __forceinline__ void load_cell(const A& a, int i, double* H) {
+  const double* src = a.cfg ? a.cells + 9L * a.cfg[i] : a.H;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) H[k] = src[k];
+}
+
 // Fixed-order tree sum of a workgroup's values (deterministic); blockDim.x a power of two.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* __restrict__ sh) {

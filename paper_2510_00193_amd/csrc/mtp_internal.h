@@ -17,7 +17,11 @@ struct SysArgs {
   const int* nj;          // [P]
   const int* shift;       // [P] packed int8 x3
   const double* radial;   // [nsp][nsp][nmu][ncheb]
-  double H[9];            // rows = lattice vectors
+  double H[9];            // rows = lattice vectors (single system)
+  const double* cells;    // [n_cfg][9] per-configuration cells (batches), or null
+  const int* cfg;         // [N] configuration of each atom (batches), or null
+  const int* perm;        // [N] processing order: lane k of the sweep takes atom perm[k], or null
+  const double* ebar;     // [n_cfg] per-configuration energy cotangent (batches), or null
   double sa, sb, rcut;    // u = sa r + sb
   int nsp, nmu, ncheb;
 };
@@ -26,12 +30,12 @@ struct SysArgs {
 // arrays of that type; energies, pair gradients and virial partials stay binary64).
 struct ChainOps {
   void (*moments)(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s);
-  void (*prog_fwd)(const void* m, long ld, int i0, int n, const int* species, const double* xi,
-                   const double* shift, int nsp, double* e_atom, void* cbar, double* bout,
-                   hipStream_t s);
+  void (*prog_fwd)(const void* m, long ld, int i0, int n, const int* perm, const int* species,
+                   const double* xi, const double* shift, int nsp, double* e_atom, void* cbar,
+                   double* bout, hipStream_t s);
   void (*prog_rev)(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s);
   void (*backward)(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
-                   int acc, double* wpart, hipStream_t s);
+                   int acc, double* wpart, double* watom, hipStream_t s);
 };
 
 // Launchers of one compiled level (filled in by the level's translation unit).
@@ -41,8 +45,8 @@ struct LevelOps {
   // parameter adjoint
   void (*tan_moments)(int grp, const SysArgs& a, const double* fbar, int i0, int n, double* md,
                       long ld, hipStream_t s);
-  void (*tan_forward)(const double* m, const double* md, long ld, int n, const double* xi,
-                      double ebar, double* out, double* cbard, hipStream_t s);
+  void (*tan_forward)(const SysArgs& a, const double* m, const double* md, long ld, int i0, int n,
+                      const double* xi, double ebar, double* out, double* cbard, hipStream_t s);
   void (*tan_reverse)(int grp, const double* m, const double* md, long ld, int n, const double* cb,
                       const double* cbd, double* mbd, hipStream_t s);
   void (*adj_pairs)(int grp, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
@@ -67,6 +71,14 @@ int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int ns
 int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, double rcut,
              NbrWork* w, const int* off, int* nj, int* shift, int* rev, long long total,
              hipStream_t s);
+// Batched build (image path per configuration): counts (synchronizes), then asks alloc for the
+// j/shift/rev arrays of *total pairs (slots 0, 1, 2) and fills them.  flags as for nbr_count;
+// when a flag is set nothing is filled.
+int nbr_batch_build(const double* pos, const int* species, int nsp, int n, const int* cfg,
+                    const int* atom_off, const double* cells, const double* cinv, const double* reach,
+                    double rcut, NbrWork* w, int* off, int** nj, int** shift, int** rev,
+                    long long* total, int* flags, int* (*alloc)(void* ctx, int slot, long long n),
+                    void* ctx, hipStream_t s);
 NbrWork* nbr_work_create();
 void nbr_work_destroy(NbrWork* w);
 
@@ -80,6 +92,12 @@ void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream
 void launch_rowsum(const double* x, long rs, long es, long n, int rows, double* out, long os,
                    hipStream_t s);
 void launch_species_grad(const int* species, int n, int nsp, double ebar, double* out, hipStream_t s);
+void launch_segsum(const double* x, long stride, const int* seg_off, int nseg, int ncomp, double* out,
+                   long os, hipStream_t s);
+void launch_loss(const double* e, const double* e0, int ncfg, const double* f, const double* f0, long n,
+                 double* ebar, double* fbar, double* part_cfg, double* part_atoms, hipStream_t s);
+void launch_species_grad_cfg(const int* species, const int* cfg, const double* ebar, int n, int nsp,
+                             double* out, hipStream_t s);
 
 // grade (mtp_grade.hip)
 void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,

@@ -48,7 +48,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  const int i = i0 + li;
+  const int i = atom_at(a, i0 + li);
+  double H[9];
+  load_cell(a, i, H);
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   R m[NG];
 #pragma unroll
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
     unpack_shift(a.shift[p], n1, n2, n3);
     double dx, dy, dz;
     pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2, n3,
-                      a.H, dx, dy, dz);
+                      H, dx, dy, dz);
     const double r = sqrt(dist2_exact(dx, dy, dz));
     const int zj = clamp_species(a.species[j], a.nsp);
     R f[L::NMU];
@@ -77,7 +79,8 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
 // ---------------------------------------------------------------------------- program forward
 template <class L, class R>
 __global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const R* __restrict__ mom, long ld,
-                                                            int i0, int n, const int* __restrict__ species,
+                                                            int i0, int n, const int* __restrict__ perm,
+                                                            const int* __restrict__ species,
                                                             const double* __restrict__ xi,
                                                             const double* __restrict__ shift, int nsp,
                                                             double* __restrict__ e_atom,
@@ -92,7 +95,8 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const R* __restrict_
   R Cb[L::NCOMP];
   const double e = bout ? L::template products<true, R>(C, xi, Cb, bout + li, ld)
                         : L::template products<false, R>(C, xi, Cb, nullptr, ld);
-  e_atom[i0 + li] = e + shift[clamp_species(species[i0 + li], nsp)];
+  const int i = perm ? perm[i0 + li] : i0 + li;
+  e_atom[i] = e + shift[clamp_species(species[i], nsp)];
 #pragma unroll
   for (int q = 0; q < L::NCOMP; ++q) cbar[(long)q * ld + li] = Cb[q];
 }
@@ -124,7 +128,8 @@ template <class L, int G, class R>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
                                                          const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
-                                                         double* __restrict__ wpart) {
+                                                         double* __restrict__ wpart,
+                                                         double* __restrict__ watom) {
   __shared__ R csh[kMaxRadial];
   __shared__ double red[kLaneBlock];
   stage_radial(a, csh);
@@ -133,7 +138,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   double w[6] = {0, 0, 0, 0, 0, 0};
   if (li < n) {
-    const int i = i0 + li;
+    const int i = atom_at(a, i0 + li);
+    double H[9];
+    load_cell(a, i, H);
     R mb[NG];
 #pragma unroll
     for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li];
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
       unpack_shift(a.shift[p], n1, n2, n3);
       double dx, dy, dz;
       pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2,
-                        n3, a.H, dx, dy, dz);
+                        n3, H, dx, dy, dz);
       const double r = sqrt(dist2_exact(dx, dy, dz));
       const int zj = clamp_species(a.species[j], a.nsp);
       R f[L::NMU], fp[L::NMU];
@@ -174,6 +181,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
       w[4] -= dx * gz;
       w[5] -= dy * gz;
     }
+    if (watom) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) watom[6L * i + k] = accumulate ? watom[6L * i + k] + w[k] : w[k];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -194,7 +205,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  const int i = i0 + li;
+  const int i = atom_at(a, i0 + li);
+  double H[9];
+  load_cell(a, i, H);
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   double md[NG];
 #pragma unroll
@@ -208,7 +221,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
     unpack_shift(a.shift[p], n1, n2, n3);
     double dx, dy, dz;
     pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2, n3,
-                      a.H, dx, dy, dz);
+                      H, dx, dy, dz);
     const double r = sqrt(dist2_exact(dx, dy, dz));
     const int zj = clamp_species(a.species[j], a.nsp);
     double f[L::NMU], fp[L::NMU];
@@ -226,12 +239,19 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
 template <class L>
 __global__ __launch_bounds__(kLaneBlock) void k_tan_forward(const double* __restrict__ mom,
                                                             const double* __restrict__ mdot, long ld,
-                                                            int n, const double* __restrict__ xi,
+                                                            int i0, int n, const int* __restrict__ perm,
+                                                            const int* __restrict__ cfg,
+                                                            const double* __restrict__ ebar_cfg,
+                                                            const double* __restrict__ xi,
                                                             double ebar, double* __restrict__ out,
                                                             double* __restrict__ cbard) {
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
+  if (ebar_cfg) {
+    const int i = perm ? perm[i0 + li] : i0 + li;
+    ebar = ebar_cfg[cfg ? cfg[i] : 0];
+  }
   GlobalMoments<double> M{mom + li, ld}, Md{mdot + li, ld};
   double C[L::NCOMP], Cd[L::NCOMP];
   L::template fwd_tan<double>(M, Md, C, Cd);
@@ -289,7 +309,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
   constexpr int NMU = L::NMU;
   const int nq = a.ncheb;
   const bool live = li < n;
-  const int i = i0 + (live ? li : 0);
+  const int i = atom_at(a, i0 + (live ? li : 0));
+  double H[9];
+  load_cell(a, i, H);
+  if (a.ebar) ebar = a.ebar[a.cfg ? a.cfg[i] : 0];
   double mb[NG], mbd[NG];
 #pragma unroll
   for (int e = 0; e < NG; ++e) {
@@ -311,7 +334,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
       unpack_shift(a.shift[p], n1, n2, n3);
       double dx, dy, dz;
       pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2,
-                        n3, a.H, dx, dy, dz);
+                        n3, H, dx, dy, dz);
       const double r = sqrt(dist2_exact(dx, dy, dz));
       const double ex = fbar[3 * j] - fix, ey = fbar[3 * j + 1] - fiy, ez = fbar[3 * j + 2] - fiz;
       const double rdot = (dx * ex + dy * ey + dz * ez) / r;
@@ -376,10 +399,10 @@ void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipSt
 }
 template <class L, int G, class R>
 void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
-                       int acc, double* wpart, hipStream_t s) {
+                       int acc, double* wpart, double* watom, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
   hipLaunchKernelGGL((k_backward<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (const R*)mb,
-                     ld, g, acc, wpart);
+                     ld, g, acc, wpart, watom);
 }
 
 template <class L, class R, size_t... Gs>
@@ -394,9 +417,10 @@ void dispatch_rev(int g, const void* m, long ld, int n, const void* cb, void* mb
 }
 template <class L, class R, size_t... Gs>
 void dispatch_backward(int g, const SysArgs& a, int i0, int n, const void* mb, long ld,
-                       double* gout, int acc, double* wpart, hipStream_t s,
+                       double* gout, int acc, double* wpart, double* watom, hipStream_t s,
                        std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R>(a, i0, n, mb, ld, gout, acc, wpart, s) : void()),
+  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R>(a, i0, n, mb, ld, gout, acc, wpart, watom, s)
+                 : void()),
    ...);
 }
 
@@ -405,19 +429,19 @@ struct EnergyChain {
   static void moments(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
     dispatch_moments<L, R>(g, a, i0, n, m, ld, s, std::make_index_sequence<L::NGROUP>{});
   }
-  static void prog_fwd(const void* m, long ld, int i0, int n, const int* species, const double* xi,
-                       const double* shift, int nsp, double* e_atom, void* cbar, double* bout,
-                       hipStream_t s) {
+  static void prog_fwd(const void* m, long ld, int i0, int n, const int* perm, const int* species,
+                       const double* xi, const double* shift, int nsp, double* e_atom, void* cbar,
+                       double* bout, hipStream_t s) {
     const int nb = (n + kLaneBlock - 1) / kLaneBlock;
     hipLaunchKernelGGL((k_program_fwd<L, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, i0, n,
-                       species, xi, shift, nsp, e_atom, (R*)cbar, bout);
+                       perm, species, xi, shift, nsp, e_atom, (R*)cbar, bout);
   }
   static void prog_rev(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s) {
     dispatch_rev<L, R>(g, m, ld, n, cb, mb, s, std::make_index_sequence<L::NGROUP>{});
   }
   static void backward(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* gout,
-                       int acc, double* wpart, hipStream_t s) {
-    dispatch_backward<L, R>(grp, a, i0, n, mb, ld, gout, acc, wpart, s,
+                       int acc, double* wpart, double* watom, hipStream_t s) {
+    dispatch_backward<L, R>(grp, a, i0, n, mb, ld, gout, acc, wpart, watom, s,
                             std::make_index_sequence<L::NGROUP>{});
   }
   static ChainOps ops() { return ChainOps{&moments, &prog_fwd, &prog_rev, &backward}; }
@@ -440,11 +464,11 @@ struct LevelImpl {
                           hipStream_t s) {
     tan_moments_d(g, a, fbar, i0, n, md, ld, s, std::make_index_sequence<L::NGROUP>{});
   }
-  static void tan_forward(const double* m, const double* md, long ld, int n, const double* xi, double ebar,
-                          double* out, double* cbard, hipStream_t s) {
+  static void tan_forward(const SysArgs& a, const double* m, const double* md, long ld, int i0, int n,
+                          const double* xi, double ebar, double* out, double* cbard, hipStream_t s) {
     const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-    hipLaunchKernelGGL((k_tan_forward<L>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, n, xi, ebar, out,
-                       cbard);
+    hipLaunchKernelGGL((k_tan_forward<L>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, i0, n, a.perm, a.cfg,
+                       a.ebar, xi, ebar, out, cbard);
   }
   template <int G>
   static void tan_reverse_g(const double* m, const double* md, long ld, int n, const double* cb,

@@ -65,21 +65,23 @@ __global__ void k_frac(const double* __restrict__ pos, const int* __restrict__ s
 
 template <bool FILL>
 __device__ __forceinline__ int image_row(int i, const double* __restrict__ pos,
-                                         const double* __restrict__ s, int n, const PlanArgs& pa,
-                                         int* __restrict__ nj, int* __restrict__ shift,
+                                         const double* __restrict__ s, int jlo, int jhi,
+                                         const double* __restrict__ H, const double* __restrict__ reach,
+                                         double rc2, int* __restrict__ nj, int* __restrict__ shift,
                                          long long* __restrict__ key, int base,
                                          int* __restrict__ flag) {
   const double six = s[3 * i], siy = s[3 * i + 1], siz = s[3 * i + 2];
   const double rix = pos[3 * i], riy = pos[3 * i + 1], riz = pos[3 * i + 2];
+  const double re0 = reach[0], re1 = reach[1], re2 = reach[2];
   int cnt = 0;
-  for (int j = 0; j < n; ++j) {
+  for (int j = jlo; j < jhi; ++j) {
     const double ds0 = s[3 * j] - six, ds1 = s[3 * j + 1] - siy, ds2 = s[3 * j + 2] - siz;
-    const int lo0 = (int)ceil(-pa.reach[0] - ds0 - kImageMargin);
-    const int hi0 = (int)floor(pa.reach[0] - ds0 + kImageMargin);
-    const int lo1 = (int)ceil(-pa.reach[1] - ds1 - kImageMargin);
-    const int hi1 = (int)floor(pa.reach[1] - ds1 + kImageMargin);
-    const int lo2 = (int)ceil(-pa.reach[2] - ds2 - kImageMargin);
-    const int hi2 = (int)floor(pa.reach[2] - ds2 + kImageMargin);
+    const int lo0 = (int)ceil(-re0 - ds0 - kImageMargin);
+    const int hi0 = (int)floor(re0 - ds0 + kImageMargin);
+    const int lo1 = (int)ceil(-re1 - ds1 - kImageMargin);
+    const int hi1 = (int)floor(re1 - ds1 + kImageMargin);
+    const int lo2 = (int)ceil(-re2 - ds2 - kImageMargin);
+    const int hi2 = (int)floor(re2 - ds2 + kImageMargin);
     if (min(lo0, min(lo1, lo2)) < -127 || max(hi0, max(hi1, hi2)) > 127) {
       // shifts must fit the packed int8 fields; the count pass reports it
       if (!FILL) flag[2] = 1;
@@ -91,8 +93,8 @@ __device__ __forceinline__ int image_row(int i, const double* __restrict__ pos,
         for (int n3 = lo2; n3 <= hi2; ++n3) {
           if (j == i && n1 == 0 && n2 == 0 && n3 == 0) continue;
           double dx, dy, dz;
-          pair_displacement(rix, riy, riz, rjx, rjy, rjz, n1, n2, n3, pa.H, dx, dy, dz);
-          if (dist2_exact(dx, dy, dz) < pa.rc2) {
+          pair_displacement(rix, riy, riz, rjx, rjy, rjz, n1, n2, n3, H, dx, dy, dz);
+          if (dist2_exact(dx, dy, dz) < rc2) {
             if (FILL) {
               const int p = base + cnt;
               nj[p] = j;
@@ -110,7 +112,7 @@ __global__ void k_image_count(const double* __restrict__ pos, const double* __re
                               PlanArgs pa, int* __restrict__ counts, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  counts[i] = image_row<false>(i, pos, s, n, pa, nullptr, nullptr, nullptr, 0, flag);
+  counts[i] = image_row<false>(i, pos, s, 0, n, pa.H, pa.reach, pa.rc2, nullptr, nullptr, nullptr, 0, flag);
 }
 
 __global__ void k_image_fill(const double* __restrict__ pos, const double* __restrict__ s, int n,
@@ -118,7 +120,48 @@ __global__ void k_image_fill(const double* __restrict__ pos, const double* __res
                              int* __restrict__ shift, long long* __restrict__ key) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  image_row<true>(i, pos, s, n, pa, nj, shift, key, off[i], nullptr);
+  image_row<true>(i, pos, s, 0, n, pa.H, pa.reach, pa.rc2, nj, shift, key, off[i], nullptr);
+}
+
+// ---------------------------------------------------------------- batches (image path per configuration)
+// cells/cinv: [n_cfg][9], reach: [n_cfg][3], atom_off: [n_cfg + 1], cfg: [N]
+__global__ void k_batch_frac(const double* __restrict__ pos, const int* __restrict__ species, int nsp,
+                             const int* __restrict__ cfg, const double* __restrict__ cinv, int n,
+                             double* __restrict__ s, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) flag[0] = 1;
+  if (species[i] < 0 || species[i] >= nsp) flag[1] = 1;
+  const double* Hinv = cinv + 9L * cfg[i];
+  double f[3];
+  frac_of(pos, i, Hinv, f);
+  s[3 * i] = f[0];
+  s[3 * i + 1] = f[1];
+  s[3 * i + 2] = f[2];
+}
+
+__global__ void k_batch_count(const double* __restrict__ pos, const double* __restrict__ s,
+                              const int* __restrict__ cfg, const int* __restrict__ atom_off,
+                              const double* __restrict__ cells, const double* __restrict__ reach,
+                              double rc2, int n, int* __restrict__ counts, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cfg[i];
+  counts[i] = image_row<false>(i, pos, s, atom_off[c], atom_off[c + 1], cells + 9L * c, reach + 3L * c,
+                               rc2, nullptr, nullptr, nullptr, 0, flag);
+}
+
+__global__ void k_batch_fill(const double* __restrict__ pos, const double* __restrict__ s,
+                             const int* __restrict__ cfg, const int* __restrict__ atom_off,
+                             const double* __restrict__ cells, const double* __restrict__ reach,
+                             double rc2, int n, const int* __restrict__ off, int* __restrict__ nj,
+                             int* __restrict__ shift, long long* __restrict__ key) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cfg[i];
+  image_row<true>(i, pos, s, atom_off[c], atom_off[c + 1], cells + 9L * c, reach + 3L * c, rc2, nj,
+                  shift, key, off[i], nullptr);
 }
 
 // ---------------------------------------------------------------- cell path
@@ -526,6 +569,45 @@ int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, dou
   }
   if (rev && total > 0)
     hipLaunchKernelGGL(k_rev, dim3(gp), dim3(kNT), 0, s, total, off, rowid, skey, rev);
+  if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
+  return 0;
+}
+
+int nbr_batch_build(const double* pos, const int* species, int nsp, int n, const int* cfg,
+                    const int* atom_off, const double* cells, const double* cinv, const double* reach,
+                    double rcut, NbrWork* w, int* off, int** nj, int** shift, int** rev,
+                    long long* total, int* flags, int* (*alloc)(void* ctx, int slot, long long n),
+                    void* ctx, hipStream_t s) {
+  int* counts = w->get<int>(S_COUNTS, n);
+  int* flag = w->get<int>(S_FLAG, 4);
+  double* sfrac = w->get<double>(S_FRAC, 3L * n);
+  if (!counts || !flag || !sfrac) return MTP_ERR_OOM;
+  (void)hipMemsetAsync(flag, 0, 4 * sizeof(int), s);
+  const double rc2 = rcut * rcut;
+  const int gb = (n + kNT - 1) / kNT;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_batch_frac, dim3(gb), dim3(kNT), 0, s, pos, species, nsp, cfg, cinv, n, sfrac, flag);
+    hipLaunchKernelGGL(k_batch_count, dim3(gb), dim3(kNT), 0, s, pos, sfrac, cfg, atom_off, cells, reach,
+                       rc2, n, counts, flag);
+  }
+  int rc = scan_counts(w, counts, n, off, total, s);
+  if (rc) return rc;
+  if (hipMemcpyAsync(flags, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return MTP_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
+  if (flags[0] || flags[1] || flags[2]) return 0;
+  *nj = alloc(ctx, 0, *total);
+  *shift = alloc(ctx, 1, *total);
+  *rev = alloc(ctx, 2, *total);
+  long long* skey = w->get<long long>(S_SKEY, *total);
+  int* rowid = w->get<int>(S_ROWID, *total);
+  if (!*nj || !*shift || !*rev || !skey || !rowid) return MTP_ERR_OOM;
+  const int gp = (int)((*total + kNT - 1) / kNT);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_batch_fill, dim3(gb), dim3(kNT), 0, s, pos, sfrac, cfg, atom_off, cells, reach,
+                       rc2, n, off, *nj, *shift, skey);
+    hipLaunchKernelGGL(k_rowid, dim3(gb), dim3(kNT), 0, s, n, off, rowid);
+  }
+  if (*total > 0) hipLaunchKernelGGL(k_rev, dim3(gp), dim3(kNT), 0, s, *total, off, rowid, skey, *rev);
   if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
   return 0;
 }

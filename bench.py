@@ -64,6 +64,136 @@ def cpu_baseline(params, target_s=12.0):
                       f"same recipe and level-16 coefficients, {dt:.1f} s"}
 
 
+def _timeit(fn, steps, warmup=1):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def section_fp32(s, params, pos, sp, ref, steps):
+    """FP32-moment form on the same workload: rate, and error against the float64 path."""
+    import torch
+    from paper_2510_00193_amd import Potential
+    pot = Potential.from_params(params, precision="fp32")
+    nl = pot.neighbors(pos, sp, s.cell)
+    dt_eval = _timeit(lambda: pot.compute(pos, sp, s.cell, nlist=nl), steps)
+    dt_full = _timeit(lambda: pot.compute(pos, sp, s.cell), steps)
+    out = pot.compute(pos, sp, s.cell, nlist=nl)
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        a, b = a.double().cpu().numpy(), b.double().cpu().numpy()
+        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+    return {"value": s.n_atoms / dt_full, "unit": "atom-steps/s", "ms_per_step": dt_full * 1e3,
+            "eval_only_atom_steps_per_s": s.n_atoms / dt_eval,
+            "rel_err_vs_fp64": {"E": rel(out["energy"].reshape(1), ref["energy"].reshape(1)),
+                                "F": rel(out["forces"], ref["forces"]), "W": rel(out["virial"], ref["virial"])}}
+
+
+def section_grade(steps):
+    """Neighbourhood grade on the 250,000-atom fcc workload (prebuilt list), FP64 and FP32-split."""
+    import torch
+    from paper_2510_00193_amd import Potential, level_info
+    info = level_info(16)
+    w = wl.workload(4, info["n_alpha"], info["n_mu"])
+    (s,) = w["structures"]
+    pot = Potential.from_params(w["params"])
+    pos = torch.as_tensor(s.pos, device="cuda")
+    sp = torch.as_tensor(s.species, device="cuda")
+    ainv = torch.as_tensor(w["extra"]["active_set_inv"], device="cuda")
+    nl = pot.neighbors(pos, sp, s.cell)
+    out = {}
+    for mode in ("fp64", "fp32split"):
+        pot.grade(pos, sp, s.cell, ainv, nlist=nl, mode=mode)
+        pot.profile(True)
+        pot.profile_reset()
+        dt = _timeit(lambda: pot.grade(pos, sp, s.cell, ainv, nlist=nl, mode=mode), steps, warmup=0)
+        prof = pot.profile_read()
+        pot.profile(False)
+        ms, launches = prof["grade_gemm"]
+        flops = 2.0 * info["n_alpha"] ** 2 * s.n_atoms  # B . Ainv per evaluation
+        gemm_tf = flops / (ms * 1e-3 / steps) / 1e12
+        peak = 78.6 if mode == "fp64" else 157.3
+        out[mode] = {"value": s.n_atoms / dt, "unit": "atom-steps/s", "ms_per_step": dt * 1e3,
+                     "gemm_ms_per_step": ms / steps, "gemm_tflops": gemm_tf,
+                     "gemm_roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": peak, "unit": "TFLOP/s",
+                                       "frac": gemm_tf / peak}}
+    g64 = pot.grade(pos, sp, s.cell, ainv, nlist=nl, mode="fp64")["grade"]
+    g32 = pot.grade(pos, sp, s.cell, ainv, nlist=nl, mode="fp32split")["grade"]
+    torch.cuda.synchronize()
+    out["fp32split"]["rel_err_vs_fp64"] = float(((g32 - g64).abs() / g64.clamp(min=1.0)).max().cpu())
+    out["workload"] = f"fcc-50x50x25-3sp-L16: {s.n_atoms} atoms, n_alpha {info['n_alpha']}"
+    return out
+
+
+def section_adjoint(steps):
+    """Parameter VJP on the 16,000-atom two-species workload (prebuilt list)."""
+    import torch
+    from paper_2510_00193_amd import Potential, level_info
+    info = level_info(16)
+    w = wl.workload(2, info["n_alpha"], info["n_mu"])
+    (s,) = w["structures"]
+    pot = Potential.from_params(w["params"])
+    pos = torch.as_tensor(s.pos, device="cuda")
+    sp = torch.as_tensor(s.species, device="cuda")
+    fbar = torch.as_tensor(np.random.default_rng(2).normal(size=(s.n_atoms, 3)), device="cuda")
+    nl = pot.neighbors(pos, sp, s.cell)
+    dt = _timeit(lambda: pot.param_grad(pos, sp, s.cell, 0.5, fbar, nlist=nl), steps)
+    dt_e = _timeit(lambda: pot.compute(pos, sp, s.cell, nlist=nl), steps)
+    return {"value": s.n_atoms / dt, "unit": "atom-steps/s", "ms_per_step": dt * 1e3,
+            "eval_ms_per_step": dt_e * 1e3,
+            "workload": f"bcc-20x20x20-2sp-L16: {s.n_atoms} atoms, VJP of (E, F) w.r.t. xi, c, s"}
+
+
+def section_batch(steps, plain_sample=128):
+    """4096 triclinic configurations at level 20: batched forward + loss gradient (tuned
+    schedule, graph replay) against plain per-configuration launches."""
+    import torch
+    from paper_2510_00193_amd import Batch, Potential, level_info
+    info = level_info(20)
+    t0 = time.perf_counter()
+    w = wl.workload(5, info["n_alpha"], info["n_mu"])
+    t_gen = time.perf_counter() - t0
+    structs, params = w["structures"], w["params"]
+    off, pos, species, cells = wl.batch_arrays(structs)
+    pot = Potential.from_params(params)
+    dpos = torch.as_tensor(pos, device="cuda")
+    dsp = torch.as_tensor(species, device="cuda")
+    rng = np.random.default_rng(55)
+    e0 = torch.as_tensor(rng.normal(size=len(structs)), device="cuda")
+    f0 = torch.as_tensor(rng.normal(size=(len(pos), 3)), device="cuda")
+    b = Batch(pot, off, dpos, dsp, cells)
+    choice = b.tune()
+    out = b.outputs()
+    dt = _timeit(lambda: b.run(out, e0, f0, use_graph=True), steps)
+    # plain: one configuration at a time (its own neighbour list, forward, then the VJP)
+    sample = structs[:plain_sample]
+    plain = [(Potential.from_params(params), torch.as_tensor(x.pos, device="cuda"),
+              torch.as_tensor(x.species, device="cuda"), x.cell) for x in sample]
+
+    def plain_pass():
+        for k, (p1, ps, ss, cell) in enumerate(plain):
+            r = p1.compute(ps, ss, cell)
+            fb = 2.0 * (r["forces"] - f0[off[k]:off[k + 1]])
+            p1.param_grad(ps, ss, cell, 2.0 * float(r["energy"] - e0[k]), fb.contiguous())
+
+    dt_plain = _timeit(plain_pass, 1)
+    return {"value": len(structs) / dt, "unit": "configs/s", "ms_per_step": dt * 1e3,
+            "atoms": int(off[-1]), "pairs": b.sizes()["n_pairs"], "schedule": choice,
+            "plain": {"value": len(sample) / dt_plain, "unit": "configs/s", "sample_configs": len(sample)},
+            "speedup_vs_plain": (len(structs) / dt) / (len(sample) / dt_plain),
+            "generation_s": t_gen,
+            "workload": "4096 triclinic cells, N ~ U{8..256}, 3 species, level 20, n_cheb 10, r_cut 5.5: "
+                        "forward E/F/virial + loss gradient w.r.t. xi, c, s per step"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +201,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--rep", type=int, default=80, help="bcc repeat (80 -> 1,024,000 atoms)")
+    ap.add_argument("--sections", default="fp32,grade,adjoint,batch",
+                    help="extra sections after the headline (comma list, or 'none')")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -116,7 +248,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     n_pairs = nl.n_pairs
     for _ in range(2):
-        pot.compute(pos, sp, s.cell, nlist=nl)
+        ref64 = pot.compute(pos, sp, s.cell, nlist=nl)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -164,7 +296,22 @@ def main(argv=None):
                       "fp64_tflops": total_flops / (dt_eval / args.steps) / 1e12},
         "kernels": kernels,
     }
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
+    if "fp32" in sections:
+        print("# section fp32", file=sys.stderr, flush=True)
+        out["fp32_form"] = section_fp32(s, params, pos, sp, ref64, args.steps)
+    del nl, ref64
+    if "grade" in sections:
+        print("# section grade", file=sys.stderr, flush=True)
+        out["grade"] = section_grade(max(3, args.steps // 2))
+    if "adjoint" in sections:
+        print("# section adjoint", file=sys.stderr, flush=True)
+        out["adjoint"] = section_adjoint(args.steps)
+    if "batch" in sections:
+        print("# section batch", file=sys.stderr, flush=True)
+        out["batch"] = section_batch(max(3, args.steps // 2))
     if not args.no_cpu:
+        print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(out), flush=True)
     return 0

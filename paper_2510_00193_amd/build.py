@@ -46,15 +46,58 @@ def _write_if_changed(path, text):
         fh.write(text)
 
 
+def _unit(lv, body):
+    return (f'// Generated: part of level {lv}.\n#include "mtp_device.h"\n#include "gen/mtp_L{lv}.inc"\n'
+            f'#include "mtp_level_impl.h"\n{body}\n')
+
+
+def _assembly(lv):
+    """Translation unit that assembles the launcher table of one level."""
+    fp32 = lv in FP32_LEVELS
+    lines = ['#include "mtp_device.h"', f'#include "gen/mtp_L{lv}.inc"', '#include "mtp_internal.h"',
+             "namespace mtp {", f"ChainOps chain_ops_{lv}_f64();"]
+    if fp32:
+        lines.append(f"ChainOps chain_ops_{lv}_f32();")
+    lines.append(f"AdjOps adj_ops_{lv}();")
+    lines.append(f"void adj_fwd_{lv}(const SysArgs&, const double*, const double*, long, int, int, const double*, "
+                 "double, double*, double*, hipStream_t);")
+    for g in range(LEVELS[lv]):
+        lines.append(f"void adj_rev_{lv}_{g}(const double*, const double*, long, int, const double*, "
+                     "const double*, double*, hipStream_t);")
+    lines += [f"LevelOps level_ops_{lv}() {{", "  LevelOps o{};", f"  using L = Lv{lv};",
+              "  o.level = L::LEVEL; o.nmom = L::NMOM; o.ncomp = L::NCOMP; o.nalpha = L::NALPHA;",
+              "  o.nmu = L::NMU; o.maxnu = L::MAXNU; o.ngroup = L::NGROUP; o.triples = L::TRIPLES;",
+              f"  o.chain[0] = chain_ops_{lv}_f64();"]
+    if fp32:
+        lines.append(f"  o.chain[1] = chain_ops_{lv}_f32();")
+    lines.append(f"  o.adj = adj_ops_{lv}();")
+    lines.append(f"  o.adj.tan_forward = &adj_fwd_{lv};")
+    for g in range(LEVELS[lv]):
+        lines.append(f"  o.adj.tan_reverse[{g}] = &adj_rev_{lv}_{g};")
+    lines += ["  return o;", "}", "}  // namespace mtp", ""]
+    return f"// Generated: launcher table of level {lv}.\n" + "\n".join(lines)
+
+
+def level_units(lv):
+    """(file name, text) of the translation units of one level."""
+    units = [(f"mtp_L{lv}.hip", _assembly(lv)),
+             (f"mtp_L{lv}_f64.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, double, f64)")),
+             (f"mtp_L{lv}_adj.hip", _unit(lv, f"MTP_DEFINE_ADJ(Lv{lv}, {lv})")),
+             (f"mtp_L{lv}_tfw.hip", _unit(lv, f"MTP_DEFINE_ADJ_FWD(Lv{lv}, {lv})"))]
+    for g in range(LEVELS[lv]):
+        units.append((f"mtp_L{lv}_rev{g}.hip", _unit(lv, f"MTP_DEFINE_ADJ_REV(Lv{lv}, {lv}, {g})")))
+    if lv in FP32_LEVELS:
+        units.append((f"mtp_L{lv}_f32.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, float, f32)")))
+    return units
+
+
 def generate(levels):
     from .codegen.emit import write_level
     os.makedirs(GEN, exist_ok=True)
     for lv in levels:
         write_level(lv, GEN, LEVELS[lv])
-        _write_if_changed(os.path.join(GEN, f"mtp_L{lv}.hip"),
-                          f'// Generated: kernels of level {lv}.\n#include "mtp_device.h"\n#include "gen/mtp_L{lv}.inc"\n'
-                          f'#include "mtp_level_impl.h"\n'
-                          f'MTP_DEFINE_LEVEL(Lv{lv}, {lv}, {"true" if lv in FP32_LEVELS else "false"})\n')
+        for name, text in level_units(lv):
+            _write_if_changed(os.path.join(GEN, name), text)
     _write_if_changed(os.path.join(GEN, "levels.inc"),
                       "".join(f"MTP_LEVEL({lv})\n" for lv in levels))
 
@@ -71,8 +114,23 @@ def _compile(src, obj):
 def sources(levels):
     out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_batch.cpp", "mtp_nbr.hip", "mtp_common.hip",
                                            "mtp_grade.hip")]
-    out += [os.path.join(GEN, f"mtp_L{lv}.hip") for lv in levels]
+    for lv in levels:
+        out += [os.path.join(GEN, name) for name, _ in level_units(lv)]
     return out
+
+
+def _level_of(src):
+    """Level number of a generated level unit (mtp_L16_f64.hip -> 16), else None."""
+    base = os.path.basename(src)
+    if not base.startswith("mtp_L"):
+        return None
+    return int(base[5:].split(".")[0].split("_")[0])
+
+
+def _work_estimate(src):
+    lv = _level_of(src)
+    inc = os.path.join(GEN, f"mtp_L{lv}.inc") if lv is not None else None
+    return os.path.getsize(inc) if inc and os.path.exists(inc) else 0
 
 
 def _deps_mtime(src):
@@ -80,8 +138,9 @@ def _deps_mtime(src):
     paths = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     paths.append(os.path.join(INCLUDE, "mtp.h"))
     base = os.path.basename(src)
-    if base.startswith("mtp_L") and base.endswith(".hip"):
-        paths.append(os.path.join(GEN, base[:-4] + ".inc"))
+    lv = _level_of(src)
+    if lv is not None:
+        paths.append(os.path.join(GEN, f"mtp_L{lv}.inc"))
     if base == "mtp_api.cpp":
         paths.append(os.path.join(GEN, "levels.inc"))
     return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
@@ -92,7 +151,7 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, incremental=False):
     levels = tuple(sorted(levels))
     generate(levels)
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sources(levels)
+    srcs = sorted(sources(levels), key=lambda p: -_work_estimate(p))  # big level units first
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -426,9 +426,11 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
   if (n > 0) {
     if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s, nullptr))) return rc;
   }
+  if ((rc = m->scratch.reserve(6 * kSumParts * sizeof(double)))) return rc;
+  double* part = (double*)m->scratch.p;
   if (energy) {
     ProfScope ps(&m->prof, P_REDUCE, s);
-    launch_sum(ea, n, 1, energy, s);
+    launch_sum_parts(ea, n, 1, 1, part, energy, s);
   }
   if (forces && n > 0) {
     ProfScope ps(&m->prof, P_GATHER, s);
@@ -437,7 +439,7 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
   if (virial) {
     ProfScope ps(&m->prof, P_REDUCE, s);
     if (n > 0)
-      launch_sum_virial((const double*)m->wpart.p, m->wblocks, virial, s);
+      launch_sum_parts((const double*)m->wpart.p, m->wblocks, 6, 6, part, virial, s);
     else
       HIP_TRY(hipMemsetAsync(virial, 0, 6 * sizeof(double), s));
   }
@@ -541,19 +543,19 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
     }
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_moments(g, a, fbar, i0, cn, mdot, ld, s);
+      L.adj.tan_moments(g, a, fbar, i0, cn, mdot, ld, s);
     }
     {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_forward(a, mom, mdot, ld, i0, cn, (const double*)m->linear.p, ebar, xout, cbard, s);
+      L.adj.tan_forward(a, mom, mdot, ld, i0, cn, (const double*)m->linear.p, ebar, xout, cbard, s);
     }
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_reverse(g, mom, mdot, ld, cn, cbar, cbard, mbard, s);
+      L.adj.tan_reverse[g](mom, mdot, ld, cn, cbar, cbard, mbard, s);
     }
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_ADJ_PAIRS, s);
-      L.adj_pairs(g, a, fbar, i0, cn, mbar, mbard, ld, ebar, cpart + part * K, s);
+      L.adj.adj_pairs(g, a, fbar, i0, cn, mbar, mbard, ld, ebar, cpart + part * K, s);
       part += cblk;
     }
     ProfScope ps(&m->prof, P_REDUCE, s);

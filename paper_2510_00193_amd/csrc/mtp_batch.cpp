@@ -221,21 +221,21 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     }
     for (int gi = 0; gi < L.ngroup; ++gi) {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_moments(gi, a, fbar, (int)i0, cn, (double*)b->mdot.p, ld, s);
+      L.adj.tan_moments(gi, a, fbar, (int)i0, cn, (double*)b->mdot.p, ld, s);
     }
     {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_forward(a, (const double*)b->mom.p, (const double*)b->mdot.p, ld, (int)i0, cn,
+      L.adj.tan_forward(a, (const double*)b->mom.p, (const double*)b->mdot.p, ld, (int)i0, cn,
                     (const double*)m->linear.p, 0.0, (double*)b->xout.p, (double*)b->cbard.p, s);
     }
     for (int gi = 0; gi < L.ngroup; ++gi) {
       ProfScope ps(&m->prof, P_TANGENT, s);
-      L.tan_reverse(gi, (const double*)b->mom.p, (const double*)b->mdot.p, ld, cn, (const double*)b->cbar.p,
+      L.adj.tan_reverse[gi]((const double*)b->mom.p, (const double*)b->mdot.p, ld, cn, (const double*)b->cbar.p,
                     (const double*)b->cbard.p, (double*)b->mbard.p, s);
     }
     for (int gi = 0; gi < L.ngroup; ++gi) {
       ProfScope ps(&m->prof, P_ADJ_PAIRS, s);
-      L.adj_pairs(gi, a, fbar, (int)i0, cn, (const double*)b->mbar.p, (const double*)b->mbard.p, ld, 0.0,
+      L.adj.adj_pairs(gi, a, fbar, (int)i0, cn, (const double*)b->mbar.p, (const double*)b->mbard.p, ld, 0.0,
                   cpart + part * KR, s);
       part += cblk;
     }

@@ -13,27 +13,64 @@ constexpr int kSumThreads = 1024;
 
 // F_k = sum over row k of (g[p] - g[rev[p]]): the atom's own pair gradients minus the
 // gradients of the pairs that have k as neighbour (newton's third law through rev).
-__global__ void k_gather(const int* __restrict__ off, const int* __restrict__ rev,
-                         const double* __restrict__ g, int n, long long npairs,
-                         double* __restrict__ f) {
+// A group of kGatherLanes lanes owns one atom: its row of g is read contiguously, the mirrored
+// entries are gathered, and the group sums with a fixed butterfly (deterministic).
+constexpr int kGatherLanes = 16;
+
+__global__ __launch_bounds__(kNT) void k_gather(const int* __restrict__ off, const int* __restrict__ rev,
+                                                const double* __restrict__ g, int n, long long npairs,
+                                                double* __restrict__ f) {
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int k = b * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  const int k = b * (kNT / kGatherLanes) + threadIdx.x / kGatherLanes;
+  const int lane = threadIdx.x % kGatherLanes;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int p = off[k]; p < off[k + 1]; ++p) {
-    fx += g[3L * p];
-    fy += g[3L * p + 1];
-    fz += g[3L * p + 2];
-    const long q = rev[p];
-    if (q >= 0 && q < npairs) {  // a list not made by this library may lack mirrors
-      fx -= g[3 * q];
-      fy -= g[3 * q + 1];
-      fz -= g[3 * q + 2];
+  if (k < n) {
+    for (int p = off[k] + lane; p < off[k + 1]; p += kGatherLanes) {
+      fx += g[3L * p];
+      fy += g[3L * p + 1];
+      fz += g[3L * p + 2];
+      const long q = rev[p];
+      if (q >= 0 && q < npairs) {  // a list not made by this library may lack mirrors
+        fx -= g[3 * q];
+        fy -= g[3 * q + 1];
+        fz -= g[3 * q + 2];
+      }
     }
   }
-  f[3L * k] = fx;
-  f[3L * k + 1] = fy;
-  f[3L * k + 2] = fz;
+#pragma unroll
+  for (int s = kGatherLanes / 2; s > 0; s >>= 1) {
+    fx += __shfl_xor(fx, s, kGatherLanes);
+    fy += __shfl_xor(fy, s, kGatherLanes);
+    fz += __shfl_xor(fz, s, kGatherLanes);
+  }
+  if (k < n && lane == 0) {
+    f[3L * k] = fx;
+    f[3L * k + 1] = fy;
+    f[3L * k + 2] = fz;
+  }
+}
+
+// Two-level fixed-order sum: kPartBlocks workgroups each sum a fixed contiguous slice, then one
+// workgroup sums the partials.  out[c] for components c of a strided array (blockIdx.y).
+constexpr int kPartBlocks = 256;
+
+__global__ __launch_bounds__(kNT) void k_sum_part(const double* __restrict__ x, long n, long stride,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[kNT];
+  const int c = blockIdx.y;
+  const long per = (n + kPartBlocks - 1) / kPartBlocks;
+  const long lo = (long)blockIdx.x * per, hi = min(n, lo + per);
+  double acc = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += kNT) acc += x[i * stride + c];
+  const double v = block_sum<kNT>(acc, sh);
+  if (threadIdx.x == 0) part[(long)c * kPartBlocks + blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kNT) void k_sum_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kNT];
+  const int c = blockIdx.x;
+  const double v = block_sum<kNT>(threadIdx.x < kPartBlocks ? part[(long)c * kPartBlocks + threadIdx.x] : 0.0, sh);
+  if (threadIdx.x == 0) out[c] = v;
 }
 
 // one workgroup: thread t sums x[t], x[t + T], ... then a fixed tree
@@ -155,8 +192,15 @@ void launch_species_grad(const int* species, int n, int nsp, double ebar, double
 void launch_gather_forces(const int* off, const int* rev, const double* g, int n, long long npairs,
                           double* forces, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather, dim3((n + kNT - 1) / kNT), dim3(kNT), 0, s, off, rev, g, n, npairs,
-                     forces);
+  const int per = kNT / kGatherLanes;
+  hipLaunchKernelGGL(k_gather, dim3((n + per - 1) / per), dim3(kNT), 0, s, off, rev, g, n, npairs, forces);
+}
+
+// out[c] = sum_i x[i * stride + c] for c < ncomp; part holds ncomp * kPartBlocks doubles.
+void launch_sum_parts(const double* x, long n, long stride, int ncomp, double* part, double* out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_part, dim3(kPartBlocks, ncomp), dim3(kNT), 0, s, x, n, stride, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(ncomp), dim3(kNT), 0, s, part, out);
 }
 
 void launch_sum(const double* x, long n, long stride, double* out, hipStream_t s) {

@@ -6,6 +6,7 @@ namespace mtp {
 
 constexpr int kMaxSpecies = 8;
 constexpr int kMaxMu = 8;
+constexpr int kMaxGroups = 4;    // moment groups per level
 constexpr int kMaxRadial = 1024;  // doubles of the staged c[z_i][z_j][mu][b] table
 constexpr int kMaxChebHost = 16;
 
@@ -38,19 +39,24 @@ struct ChainOps {
                    int acc, double* wpart, double* watom, hipStream_t s);
 };
 
-// Launchers of one compiled level (filled in by the level's translation unit).
-struct LevelOps {
-  int level, nmom, ncomp, nalpha, nmu, maxnu, ngroup, triples;
-  ChainOps chain[2];  // [0] binary64, [1] binary32 moments (null when not compiled)
-  // parameter adjoint
+// Parameter-adjoint launchers of one level (binary64).
+struct AdjOps {
   void (*tan_moments)(int grp, const SysArgs& a, const double* fbar, int i0, int n, double* md,
                       long ld, hipStream_t s);
   void (*tan_forward)(const SysArgs& a, const double* m, const double* md, long ld, int i0, int n,
                       const double* xi, double ebar, double* out, double* cbard, hipStream_t s);
-  void (*tan_reverse)(int grp, const double* m, const double* md, long ld, int n, const double* cb,
-                      const double* cbd, double* mbd, hipStream_t s);
+  // one launcher per moment group (compiled in separate units)
+  void (*tan_reverse[kMaxGroups])(const double* m, const double* md, long ld, int n, const double* cb,
+                                  const double* cbd, double* mbd, hipStream_t s);
   void (*adj_pairs)(int grp, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                     const double* mbd, long ld, double ebar, double* cpart, hipStream_t s);
+};
+
+// Launchers of one compiled level (assembled from the level's translation units).
+struct LevelOps {
+  int level, nmom, ncomp, nalpha, nmu, maxnu, ngroup, triples;
+  ChainOps chain[2];  // [0] binary64, [1] binary32 moments (null when not compiled)
+  AdjOps adj;
 };
 
 // neighbour list (mtp_nbr.hip)
@@ -86,6 +92,10 @@ void nbr_work_destroy(NbrWork* w);
 void launch_gather_forces(const int* off, const int* rev, const double* g, int n, long long npairs,
                           double* forces, hipStream_t s);
 void launch_sum(const double* x, long n, long stride, double* out, hipStream_t s);
+// Two-level deterministic sums of ncomp strided components (part: ncomp * kSumParts doubles).
+constexpr int kSumParts = 256;
+void launch_sum_parts(const double* x, long n, long stride, int ncomp, double* part, double* out,
+                      hipStream_t s);
 void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream_t s);
 
 // out[r * os] = sum_{k < n} x[r * rs + k * es], r < rows (deterministic)

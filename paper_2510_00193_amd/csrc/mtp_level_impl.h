@@ -39,6 +39,46 @@ __device__ __forceinline__ void stage_radial(const SysArgs& a, R* sh) {
   __syncthreads();
 }
 
+// Walk the CSR row of atom i with software prefetch: the partner indices are loaded two pairs
+// ahead and the partner position/species one pair ahead, so the gather latency overlaps the
+// arithmetic of the current pair.  body(p, j, zj, dx, dy, dz, r) sees the exact displacement.
+template <class F>
+__device__ __forceinline__ void for_pairs(const SysArgs& a, int i, const double* H, double rix, double riy,
+                                          double riz, F&& body) {
+  const int p0 = a.off[i], p1 = a.off[i + 1];
+  if (p0 >= p1) return;
+  int jA = a.nj[p0], shA = a.shift[p0];
+  double xA = a.pos[3 * jA], yA = a.pos[3 * jA + 1], zA = a.pos[3 * jA + 2];
+  int sA = a.species[jA];
+  int jB = 0, shB = 0;
+  if (p0 + 1 < p1) {
+    jB = a.nj[p0 + 1];
+    shB = a.shift[p0 + 1];
+  }
+  for (int p = p0; p < p1; ++p) {
+    const int j = jA, sh = shA, sj = sA;
+    const double xj = xA, yj = yA, zj = zA;
+    if (p + 1 < p1) {
+      xA = a.pos[3 * jB];
+      yA = a.pos[3 * jB + 1];
+      zA = a.pos[3 * jB + 2];
+      sA = a.species[jB];
+      jA = jB;
+      shA = shB;
+    }
+    if (p + 2 < p1) {
+      jB = a.nj[p + 2];
+      shB = a.shift[p + 2];
+    }
+    int n1, n2, n3;
+    unpack_shift(sh, n1, n2, n3);
+    double dx, dy, dz;
+    pair_displacement(rix, riy, riz, xj, yj, zj, n1, n2, n3, H, dx, dy, dz);
+    const double r = sqrt(dist2_exact(dx, dy, dz));
+    body(p, j, clamp_species(sj, a.nsp), dx, dy, dz, r);
+  }
+}
+
 // ---------------------------------------------------------------------------- moments
 template <class L, int G, class R>
 __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
@@ -57,21 +97,12 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
   for (int e = 0; e < NG; ++e) m[e] = R(0);
   const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
-  const int p0 = a.off[i], p1 = a.off[i + 1];
-  for (int p = p0; p < p1; ++p) {
-    const int j = a.nj[p];
-    int n1, n2, n3;
-    unpack_shift(a.shift[p], n1, n2, n3);
-    double dx, dy, dz;
-    pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2, n3,
-                      H, dx, dy, dz);
-    const double r = sqrt(dist2_exact(dx, dy, dz));
-    const int zj = clamp_species(a.species[j], a.nsp);
+  const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
+  for_pairs(a, i, H, rix, riy, riz, [&](int, int, int zj, double dx, double dy, double dz, double r) {
     R f[L::NMU];
-    radial_values<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut,
-                             csh + (zi * a.nsp + zj) * L::NMU * a.ncheb, a.ncheb, f);
+    radial_values<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f);
     L::template acc_moments<G>(m, f, (R)dx, (R)dy, (R)dz);
-  }
+  });
 #pragma unroll
   for (int e = 0; e < NG; ++e) mout[(long)(LO + e) * ld + li] = m[e];
 }
@@ -146,19 +177,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li];
     const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
     const int zi = clamp_species(a.species[i], a.nsp);
-    const int p0 = a.off[i], p1 = a.off[i + 1];
-    for (int p = p0; p < p1; ++p) {
-      const int j = a.nj[p];
-      int n1, n2, n3;
-      unpack_shift(a.shift[p], n1, n2, n3);
-      double dx, dy, dz;
-      pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2,
-                        n3, H, dx, dy, dz);
-      const double r = sqrt(dist2_exact(dx, dy, dz));
-      const int zj = clamp_species(a.species[j], a.nsp);
+    const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
+    for_pairs(a, i, H, rix, riy, riz, [&](int p, int, int zj, double dx, double dy, double dz, double r) {
       R f[L::NMU], fp[L::NMU];
-      radial<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut,
-                        csh + (zi * a.nsp + zj) * L::NMU * a.ncheb, a.ncheb, f, fp);
+      radial<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f, fp);
       R rgx = R(0), rgy = R(0), rgz = R(0), ru = R(0);
       L::template pair_grad<G>(mb, f, fp, (R)dx, (R)dy, (R)dz, rgx, rgy, rgz, ru);
       const double ur = (double)ru / r;
@@ -180,7 +202,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
       w[3] -= dx * gy;
       w[4] -= dx * gz;
       w[5] -= dy * gz;
-    }
+    });
     if (watom) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) watom[6L * i + k] = accumulate ? watom[6L * i + k] + w[k] : w[k];
@@ -215,22 +237,13 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
   const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
   const double fix = fbar[3 * i], fiy = fbar[3 * i + 1], fiz = fbar[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
-  for (int p = a.off[i]; p < a.off[i + 1]; ++p) {
-    const int j = a.nj[p];
-    int n1, n2, n3;
-    unpack_shift(a.shift[p], n1, n2, n3);
-    double dx, dy, dz;
-    pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2, n3,
-                      H, dx, dy, dz);
-    const double r = sqrt(dist2_exact(dx, dy, dz));
-    const int zj = clamp_species(a.species[j], a.nsp);
+  for_pairs(a, i, H, rix, riy, riz, [&](int, int j, int zj, double dx, double dy, double dz, double r) {
     double f[L::NMU], fp[L::NMU];
-    radial<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb,
-                           a.ncheb, f, fp);
+    radial<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb, a.ncheb, f, fp);
     const double ex = fbar[3 * j] - fix, ey = fbar[3 * j + 1] - fiy, ez = fbar[3 * j + 2] - fiz;
     const double rdot = (dx * ex + dy * ey + dz * ez) / r;
     L::template tan_moments<G>(md, f, fp, dx, dy, dz, ex, ey, ez, rdot);
-  }
+  });
 #pragma unroll
   for (int e = 0; e < NG; ++e) mdot[(long)(LO + e) * ld + li] = md[e];
 }
@@ -447,8 +460,8 @@ struct EnergyChain {
   static ChainOps ops() { return ChainOps{&moments, &prog_fwd, &prog_rev, &backward}; }
 };
 
-template <class L, bool WITH_FP32>
-struct LevelImpl {
+template <class L>
+struct AdjImpl {
   template <int G>
   static void tan_moments_g(const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
                             hipStream_t s) {
@@ -476,15 +489,6 @@ struct LevelImpl {
     const int nb = (n + kLaneBlock - 1) / kLaneBlock;
     hipLaunchKernelGGL((k_tan_reverse<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, n, cb, cbd, mbd);
   }
-  template <size_t... Gs>
-  static void tan_reverse_d(int g, const double* m, const double* md, long ld, int n, const double* cb,
-                            const double* cbd, double* mbd, hipStream_t s, std::index_sequence<Gs...>) {
-    ((g == (int)Gs ? tan_reverse_g<(int)Gs>(m, md, ld, n, cb, cbd, mbd, s) : void()), ...);
-  }
-  static void tan_reverse(int g, const double* m, const double* md, long ld, int n, const double* cb,
-                          const double* cbd, double* mbd, hipStream_t s) {
-    tan_reverse_d(g, m, md, ld, n, cb, cbd, mbd, s, std::make_index_sequence<L::NGROUP>{});
-  }
   template <int G>
   static void adj_pairs_g(const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                           const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
@@ -502,21 +506,9 @@ struct LevelImpl {
                         const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
     adj_pairs_d(g, a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s, std::make_index_sequence<L::NGROUP>{});
   }
-  static LevelOps ops() {
-    LevelOps o{};
-    o.level = L::LEVEL;
-    o.nmom = L::NMOM;
-    o.ncomp = L::NCOMP;
-    o.nalpha = L::NALPHA;
-    o.nmu = L::NMU;
-    o.maxnu = L::MAXNU;
-    o.ngroup = L::NGROUP;
-    o.triples = L::TRIPLES;
-    o.chain[0] = EnergyChain<L, double>::ops();
-    if constexpr (WITH_FP32) o.chain[1] = EnergyChain<L, float>::ops();
+  static AdjOps ops() {
+    AdjOps o{};
     o.tan_moments = &tan_moments;
-    o.tan_forward = &tan_forward;
-    o.tan_reverse = &tan_reverse;
     o.adj_pairs = &adj_pairs;
     return o;
   }
@@ -524,7 +516,27 @@ struct LevelImpl {
 
 }  // namespace mtp
 
-#define MTP_DEFINE_LEVEL(LV, NUM, FP32)                                  \
-  namespace mtp {                                                        \
-  LevelOps level_ops_##NUM() { return LevelImpl<LV, FP32>::ops(); }      \
+// One level is compiled as several translation units (binary64 chain, binary32 chain,
+// adjoint, assembly) so that large levels build in parallel.
+#define MTP_DEFINE_CHAIN(LV, NUM, TYPE, TAG) \
+  namespace mtp {                            \
+  ChainOps chain_ops_##NUM##_##TAG() { return EnergyChain<LV, TYPE>::ops(); } \
+  }
+#define MTP_DEFINE_ADJ(LV, NUM) \
+  namespace mtp {               \
+  AdjOps adj_ops_##NUM() { return AdjImpl<LV>::ops(); } \
+  }
+#define MTP_DEFINE_ADJ_FWD(LV, NUM) \
+  namespace mtp {                   \
+  void adj_fwd_##NUM(const SysArgs& a, const double* m, const double* md, long ld, int i0, int n, \
+                     const double* xi, double ebar, double* out, double* cbard, hipStream_t s) { \
+    AdjImpl<LV>::tan_forward(a, m, md, ld, i0, n, xi, ebar, out, cbard, s);                     \
+  }                                                                                             \
+  }
+#define MTP_DEFINE_ADJ_REV(LV, NUM, G) \
+  namespace mtp {                      \
+  void adj_rev_##NUM##_##G(const double* m, const double* md, long ld, int n, const double* cb, \
+                           const double* cbd, double* mbd, hipStream_t s) {                     \
+    AdjImpl<LV>::tan_reverse_g<G>(m, md, ld, n, cb, cbd, mbd, s);                             \
+  }                                                                                          \
   }

@@ -333,6 +333,152 @@ __global__ void k_rev(long long total, const int* __restrict__ off, const int* _
   rev[p] = found;
 }
 
+// ---------------------------------------------------------------- cell path, one workgroup per bin
+// The workgroup stages the candidates of the 27 surrounding bins in LDS once (positions,
+// indices and the image offset each candidate needs), then each wave takes one centre atom of
+// the bin: lanes test candidates, hits are compacted with a ballot into a per-wave LDS list,
+// rank-sorted by key and written as a fixed-capacity row (rows[i * cap + k]).
+constexpr int kBinThreads = 256;
+constexpr int kBinWaves = kBinThreads / 64;
+constexpr int kMaxCand = 1024;     // candidates staged per bin neighbourhood
+constexpr int kRowCap = 256;       // hits kept per centre in LDS
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_rows(const double* __restrict__ pos, PlanArgs pa,
+                                                          const int* __restrict__ img,
+                                                          const int* __restrict__ binstart,
+                                                          const int* __restrict__ binatoms, int cap,
+                                                          long long* __restrict__ rows,
+                                                          int* __restrict__ counts, int* __restrict__ flag) {
+  __shared__ double cx[kMaxCand], cy[kMaxCand], cz[kMaxCand];
+  __shared__ int cj[kMaxCand], cb0[kMaxCand], cb1[kMaxCand], cb2[kMaxCand];
+  __shared__ long long hits[kBinWaves][kRowCap];
+  __shared__ int bst[27], boff[28], bw0[27], bw1[27], bw2[27];
+  const int bid = blockIdx.x;
+  const int b2 = bid % pa.nb[2];
+  const int b1 = (bid / pa.nb[2]) % pa.nb[1];
+  const int b0 = bid / (pa.nb[2] * pa.nb[1]);
+  // the 27 surrounding bins (fixed order) and the wrap each one implies
+  if (threadIdx.x < 27) {
+    const int nbk = threadIdx.x;
+    const int d0 = nbk / 9 - 1, d1 = (nbk / 3) % 3 - 1, d2 = nbk % 3 - 1;
+    int c0 = b0 + d0, w0 = 0, c1 = b1 + d1, w1 = 0, c2 = b2 + d2, w2 = 0;
+    if (c0 < 0) { c0 += pa.nb[0]; w0 = -1; } else if (c0 >= pa.nb[0]) { c0 -= pa.nb[0]; w0 = 1; }
+    if (c1 < 0) { c1 += pa.nb[1]; w1 = -1; } else if (c1 >= pa.nb[1]) { c1 -= pa.nb[1]; w1 = 1; }
+    if (c2 < 0) { c2 += pa.nb[2]; w2 = -1; } else if (c2 >= pa.nb[2]) { c2 -= pa.nb[2]; w2 = 1; }
+    const int cid = (c0 * pa.nb[1] + c1) * pa.nb[2] + c2;
+    bst[nbk] = binstart[cid];
+    boff[nbk + 1] = binstart[cid + 1] - binstart[cid];
+    bw0[nbk] = w0;
+    bw1[nbk] = w1;
+    bw2[nbk] = w2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    boff[0] = 0;
+    for (int k = 0; k < 27; ++k) boff[k + 1] += boff[k];
+  }
+  __syncthreads();
+  const int ncand = boff[27];
+  if (ncand > kMaxCand) {
+    if (threadIdx.x == 0) flag[3] = 1;  // too dense for the staged path: caller falls back
+    return;
+  }
+  for (int k = threadIdx.x; k < ncand; k += kBinThreads) {
+    int t = 0;
+    while (boff[t + 1] <= k) ++t;
+    const int j = binatoms[bst[t] + (k - boff[t])];
+    cx[k] = pos[3 * j];
+    cy[k] = pos[3 * j + 1];
+    cz[k] = pos[3 * j + 2];
+    cj[k] = j;
+    cb0[k] = bw0[t] - img[3 * j];
+    cb1[k] = bw1[t] - img[3 * j + 1];
+    cb2[k] = bw2[t] - img[3 * j + 2];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int a0 = binstart[bid], a1 = binstart[bid + 1];
+  long long* hw = hits[wave];
+  for (int ci = a0 + wave; ci < a1; ci += kBinWaves) {
+    const int i = binatoms[ci];
+    const double rix = pos[3 * i], riy = pos[3 * i + 1], riz = pos[3 * i + 2];
+    const int oi0 = img[3 * i], oi1 = img[3 * i + 1], oi2 = img[3 * i + 2];
+    int cnt = 0;
+    for (int q0 = 0; q0 < ncand; q0 += 64) {
+      const int q = q0 + lane;
+      bool hit = false;
+      long long key = 0;
+      if (q < ncand) {
+        const int j = cj[q];
+        const int n1 = cb0[q] + oi0, n2 = cb1[q] + oi1, n3 = cb2[q] + oi2;
+        if (!(j == i && n1 == 0 && n2 == 0 && n3 == 0)) {
+          double dx, dy, dz;
+          pair_displacement(rix, riy, riz, cx[q], cy[q], cz[q], n1, n2, n3, pa.H, dx, dy, dz);
+          hit = dist2_exact(dx, dy, dz) < pa.rc2;
+          key = make_key(j, n1, n2, n3);
+        }
+      }
+      const unsigned long long mask = __ballot(hit);
+      if (hit) {
+        const int slot = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+        if (slot < kRowCap) hw[slot] = key;
+      }
+      cnt += __popcll(mask);
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    if (cnt > cap || cnt > kRowCap) {
+      if (lane == 0) flag[3] = 1;
+      if (lane == 0) counts[i] = 0;
+      continue;
+    }
+    for (int h = lane; h < cnt; h += 64) {
+      const long long k = hw[h];
+      int rank = 0;
+      for (int t = 0; t < cnt; ++t) rank += hw[t] < k;
+      rows[(long)i * cap + rank] = k;
+    }
+    if (lane == 0) counts[i] = cnt;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// CSR from the fixed-capacity rows: one wave per atom copies its sorted row and finds the
+// mirror (j, i, -n) of every pair by binary search in row j.
+__global__ __launch_bounds__(256) void k_rows_to_csr(int n, int cap, const long long* __restrict__ rows,
+                                                     const int* __restrict__ counts,
+                                                     const int* __restrict__ off, int* __restrict__ nj,
+                                                     int* __restrict__ shift, int* __restrict__ rev) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int cnt = counts[i], o = off[i];
+  for (int k = lane; k < cnt; k += 64) {
+    const long long key = rows[(long)i * cap + k];
+    const int j = (int)(key >> 24);
+    const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
+              n3 = (int)(key & 0xFF) - 128;
+    nj[o + k] = j;
+    shift[o + k] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
+    if (rev) {
+      const long long want = make_key(i, -n1, -n2, -n3);
+      const long long* rj = rows + (long)j * cap;
+      int lo = 0, hi = counts[j] - 1, found = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const long long v = rj[mid];
+        if (v == want) {
+          found = mid;
+          break;
+        }
+        if (v < want) lo = mid + 1; else hi = mid - 1;
+      }
+      rev[o + k] = found < 0 ? -1 : off[j] + found;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- exclusive scan (int)
 constexpr int kScanPer = 8;
 constexpr int kScanBlock = kNT * kScanPer;
@@ -408,13 +554,14 @@ struct NbrWork {
     return (T*)ptr[slot];
   }
   PlanArgs pa;
+  int row_cap = 0;      // capacity of the staged rows when the workgroup-per-bin path filled them
 };
 
 NbrWork* nbr_work_create() { return new NbrWork(); }
 void nbr_work_destroy(NbrWork* w) { delete w; }
 
 enum Slot { S_FRAC, S_BIN, S_IMG, S_BINCNT, S_BINSTART, S_BINFILL, S_BINATOMS, S_COUNTS, S_BSUM,
-            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG };
+            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG, S_ROWS };
 
 static void inv3(const double* H, double* I, double* det) {
   const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7],
@@ -514,10 +661,29 @@ int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int ns
                          flag);
     int rc = scan_counts(w, bincnt, nbins, binstart, nullptr, s);
     if (rc) return rc;
+    if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(kNT), 0, s, n, bin, binstart, binfill, binatoms);
+    w->row_cap = 0;
     if (n > 0) {
-      hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(kNT), 0, s, n, bin, binstart, binfill, binatoms);
-      hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart,
-                         binatoms, counts);
+      // rows of the staged path, sized from the density (a sphere of radius r_cut, 50% slack)
+      double vol = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                        H[2] * (H[3] * H[7] - H[4] * H[6]));
+      const double expect = 4.18879020478639 * rcut * rcut * rcut * n / vol;
+      int cap = (int)(1.5 * expect) + 32;
+      cap = ((cap + 31) / 32) * 32;
+      if (cap <= kRowCap) {
+        long long* rows = w->get<long long>(S_ROWS, (size_t)n * cap);
+        if (!rows) return MTP_ERR_OOM;
+        hipLaunchKernelGGL(k_bin_rows, dim3(nbins), dim3(kBinThreads), 0, s, pos, pa, img, binstart, binatoms,
+                           cap, rows, counts, flag);
+        int fl[4];
+        if (hipMemcpyAsync(fl, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return MTP_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
+        if (fl[3] == 0) w->row_cap = cap;
+        else (void)hipMemsetAsync(flag + 3, 0, sizeof(int), s);
+      }
+      if (w->row_cap == 0)
+        hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart,
+                           binatoms, counts);
     }
   } else {
     double* sfrac = w->get<double>(S_FRAC, 3L * n);
@@ -545,6 +711,15 @@ int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, dou
   long long* skey = w->get<long long>(S_SKEY, total);
   int* rowid = w->get<int>(S_ROWID, total);
   if (!skey || !rowid) return MTP_ERR_OOM;
+  if (plan.cells && w->row_cap > 0) {
+    const long long* rows = w->get<long long>(S_ROWS, 1);
+    int* counts = w->get<int>(S_COUNTS, n);
+    if (n > 0)
+      hipLaunchKernelGGL(k_rows_to_csr, dim3((n + 3) / 4), dim3(256), 0, s, n, w->row_cap, rows, counts, off, nj,
+                         shift, rev);
+    if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
+    return 0;
+  }
   if (plan.cells) {
     long long* key = w->get<long long>(S_KEY, total);
     if (!key) return MTP_ERR_OOM;

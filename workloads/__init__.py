@@ -153,43 +153,73 @@ def _random_cell(rng, n_atoms, density):
     return cell
 
 
-def _rsa_positions(rng, cell, n_atoms, d_min, max_tries):
-    """Random sequential addition with min distance d_min over all periodic images."""
+def _min_image_d2(ds, cell, single):
+    """Squared distance to the nearest image for fractional differences ds [..., 3].
+
+    After wrapping ds to [-1/2, 1/2), an image closer than half of every perpendicular
+    width must be the wrapped one (|ds_k + n_k| <= |d| / width_k < 1/2 forces n_k = 0);
+    single=True uses that, otherwise the 27 surrounding images are scanned.
+    """
+    ds = ds - np.round(ds)
+    x0 = ds @ cell
+    if single:
+        return (x0 * x0).sum(axis=-1)
+    best = None
+    for t in _IMAGES27 @ cell:
+        x = x0 + t
+        d2 = (x * x).sum(axis=-1)
+        best = d2 if best is None else np.minimum(best, d2)
+    return best
+
+
+_IMAGES27 = np.stack(np.meshgrid([-1.0, 0.0, 1.0], [-1.0, 0.0, 1.0], [-1.0, 0.0, 1.0], indexing="ij"),
+                     axis=-1).reshape(-1, 3)
+
+
+def _rsa_positions(rng, cell, n_atoms, d_min, max_rounds):
+    """Random sequential addition in rounds, minimum distance d_min over all periodic images.
+
+    Each round draws as many uniform fractional points as atoms are missing and accepts
+    them in draw order when they keep d_min from every accepted point (earlier rounds and
+    earlier points of this round).  Requires every perpendicular width > d_min, so the 27
+    images around the wrapped difference hold every image closer than d_min (self-images
+    included).  Returns None after max_rounds rounds without completion.
+    """
     widths = _perp_widths(cell)
-    if np.any(widths < d_min):
+    if np.any(widths <= d_min):
         return None
-    nhat = np.ceil(d_min / widths).astype(int) + 1
-    rng_n = [np.arange(-k, k + 1) for k in nhat]
-    imgs = np.stack(np.meshgrid(*rng_n, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
-    shifts = imgs @ cell  # [n_img, 3]
+    single = bool(np.all(widths > 2.0 * d_min))
     d2 = d_min * d_min
-    pos = np.empty((n_atoms, 3))
-    placed = 0
-    while placed < n_atoms:
-        ok = False
-        for _ in range(max_tries):
-            s = rng.uniform(0.0, 1.0, size=3)
-            x = s @ cell
-            if placed:
-                diff = pos[:placed, None, :] + shifts[None, :, :] - x[None, None, :]
-                if np.min(np.einsum("abk,abk->ab", diff, diff)) < d2:
-                    continue
-            ok = True
+    acc = np.zeros((0, 3))
+    for _ in range(max_rounds):
+        need = n_atoms - len(acc)
+        if need == 0:
             break
-        if not ok:
-            return None
-        pos[placed] = x
-        placed += 1
-    return pos
+        cand = rng.uniform(0.0, 1.0, size=(need, 3))
+        ok = np.ones(need, dtype=bool)
+        if len(acc):
+            ok &= _min_image_d2(cand[:, None, :] - acc[None, :, :], cell, single).min(axis=1) >= d2
+        close = _min_image_d2(cand[:, None, :] - cand[None, :, :], cell, single) < d2
+        np.fill_diagonal(close, False)
+        blocked = ~ok
+        keep = []
+        for k in range(need):
+            if not blocked[k]:
+                keep.append(k)
+                blocked |= close[k]
+        acc = np.concatenate([acc, cand[keep]])
+    if len(acc) < n_atoms:
+        return None
+    return acc @ cell
 
 
-def random_cell_batch(rng, n_cfg, n_min, n_max, density, d_min, n_species, max_tries=100000):
+def random_cell_batch(rng, n_cfg, n_min, n_max, density, d_min, n_species, max_rounds=200):
     """n_cfg triclinic periodic configurations with N ~ U{n_min..n_max}.
 
     Cells are lower-triangular with diagonals V^(1/3) e^u (u ~ U(-0.2, 0.2)
     recentred to zero sum) and tilts U(-0.3, 0.3) times the matching diagonal;
-    positions come from random sequential addition under a minimum image
-    distance d_min over all images (self-images included); species are
+    positions come from random sequential addition in rounds under a minimum
+    image distance d_min over all images (self-images included); species are
     i.i.d. uniform.  A cell on which placement fails is redrawn.
     Draw order per configuration: N, cell, positions, species.
     """
@@ -198,7 +228,7 @@ def random_cell_batch(rng, n_cfg, n_min, n_max, density, d_min, n_species, max_t
         n = int(rng.integers(n_min, n_max + 1))
         while True:
             cell = _random_cell(rng, n, density)
-            pos = _rsa_positions(rng, cell, n, d_min, max_tries)
+            pos = _rsa_positions(rng, cell, n, d_min, max_rounds)
             if pos is not None:
                 break
         species = rng.integers(0, n_species, size=n).astype(np.int32)

@@ -255,3 +255,42 @@ def sampled_forces(model, struct, atoms):
         fk = g[gi == k].sum(axis=0) - g[js == k].sum(axis=0)
         out.append(fk)
     return np.array(out)
+
+
+def param_vjp_chunked(model, struct, ebar, fbar, nl=None, chunk=512):
+    """The same vector-Jacobian product, accumulated over chunks of centre atoms.
+
+    With D = sum_k fbar_k . dE/dR_k = sum_i sum_j g_ij . (fbar_j - fbar_i), where g_ij is the
+    derivative of E_i by the pair displacement, ebar dE/dtheta + sum_k fbar_k . dF_k/dtheta =
+    d/dtheta sum_i (ebar E_i - D_i), and each bracket depends only on centre i's pairs; so the
+    chunks add up to the whole.  Used where the system is too large for one autograd graph.
+    """
+    if nl is None:
+        nl = _nb.neighbor_csr(struct.pos, struct.cell, model.r_cut)
+    fbar = np.asarray(fbar, dtype=np.float64)
+    z = torch.as_tensor(struct.species.astype(np.int64))
+    radial = model.radial.clone().requires_grad_(True)
+    linear = model.linear.clone().requires_grad_(True)
+    shift = model.shift.clone().requires_grad_(True)
+    acc = [torch.zeros_like(linear), torch.zeros_like(radial), torch.zeros_like(shift)]
+    off = nl["off"]
+    n = struct.n_atoms
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        p0, p1 = int(off[c0]), int(off[c1])
+        i = nl["i"][p0:p1]
+        j = nl["j"][p0:p1]
+        d = torch.as_tensor(_nb.displacements(struct.pos, struct.cell, i, j, nl["n"][p0:p1]))
+        d.requires_grad_(True)
+        ci = torch.as_tensor((i - c0).astype(np.int64))
+        zc = z[c0:c1]
+        e_i, _ = site_quantities(model, d, ci, zc, z[torch.as_tensor(j.astype(np.int64))], c1 - c0,
+                                 radial, linear, shift)
+        (g,) = torch.autograd.grad(e_i.sum(), d, create_graph=True)
+        delta = torch.as_tensor(fbar[j] - fbar[i])
+        target = float(ebar) * e_i.sum() - (g * delta).sum()
+        grads = torch.autograd.grad(target, [linear, radial, shift], allow_unused=True)
+        for a, gr in zip(acc, grads):
+            if gr is not None:
+                a += gr.detach()
+    return tuple(a.numpy() for a in acc)

@@ -20,8 +20,11 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmtp.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-# level -> number of moment-entry groups (register budget of the lane-per-atom kernels)
+# level -> moment-entry groups of the lane-per-atom kernels (register budget): a count of
+# equal ranges, or a tuple of interior boundaries of the flat moment layout
 LEVELS = {2: 1, 4: 1, 6: 1, 8: 1, 10: 1, 12: 1, 14: 1, 16: 1, 18: 2, 20: 3}
+if os.environ.get("MTP_GROUPS_L16"):
+    LEVELS[16] = tuple(int(x) for x in os.environ["MTP_GROUPS_L16"].split(","))
 # levels that also get the binary32-moment chain
 FP32_LEVELS = {2, 4, 6, 8, 10, 12, 14, 16}
 DEFAULT_LEVELS = (2, 4, 6, 8, 10, 12, 14, 16, 20)
@@ -51,28 +54,33 @@ def _unit(lv, body):
             f'#include "mtp_level_impl.h"\n{body}\n')
 
 
+def _ngroups(lv):
+    g = LEVELS[lv]
+    return len(g) + 1 if isinstance(g, tuple) else g
+
+
 def _assembly(lv):
     """Translation unit that assembles the launcher table of one level."""
     fp32 = lv in FP32_LEVELS
     lines = ['#include "mtp_device.h"', f'#include "gen/mtp_L{lv}.inc"', '#include "mtp_internal.h"',
-             "namespace mtp {", f"ChainOps chain_ops_{lv}_f64();"]
+             "namespace mtp {", f"ChainOps chain_ops_{lv}_f64();", f"ChainOps chain_ops_{lv}_b64();"]
     if fp32:
         lines.append(f"ChainOps chain_ops_{lv}_f32();")
     lines.append(f"AdjOps adj_ops_{lv}();")
     lines.append(f"void adj_fwd_{lv}(const SysArgs&, const double*, const double*, long, int, int, const double*, "
                  "double, double*, double*, hipStream_t);")
-    for g in range(LEVELS[lv]):
+    for g in range(_ngroups(lv)):
         lines.append(f"void adj_rev_{lv}_{g}(const double*, const double*, long, int, const double*, "
                      "const double*, double*, hipStream_t);")
     lines += [f"LevelOps level_ops_{lv}() {{", "  LevelOps o{};", f"  using L = Lv{lv};",
               "  o.level = L::LEVEL; o.nmom = L::NMOM; o.ncomp = L::NCOMP; o.nalpha = L::NALPHA;",
               "  o.nmu = L::NMU; o.maxnu = L::MAXNU; o.ngroup = L::NGROUP; o.triples = L::TRIPLES;",
-              f"  o.chain[0] = chain_ops_{lv}_f64();"]
+              f"  o.chain[0] = chain_ops_{lv}_f64();", f"  o.chain[2] = chain_ops_{lv}_b64();"]
     if fp32:
         lines.append(f"  o.chain[1] = chain_ops_{lv}_f32();")
     lines.append(f"  o.adj = adj_ops_{lv}();")
     lines.append(f"  o.adj.tan_forward = &adj_fwd_{lv};")
-    for g in range(LEVELS[lv]):
+    for g in range(_ngroups(lv)):
         lines.append(f"  o.adj.tan_reverse[{g}] = &adj_rev_{lv}_{g};")
     lines += ["  return o;", "}", "}  // namespace mtp", ""]
     return f"// Generated: launcher table of level {lv}.\n" + "\n".join(lines)
@@ -81,13 +89,14 @@ def _assembly(lv):
 def level_units(lv):
     """(file name, text) of the translation units of one level."""
     units = [(f"mtp_L{lv}.hip", _assembly(lv)),
-             (f"mtp_L{lv}_f64.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, double, f64)")),
+             (f"mtp_L{lv}_f64.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, double, false, f64)")),
+             (f"mtp_L{lv}_b64.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, double, true, b64)")),
              (f"mtp_L{lv}_adj.hip", _unit(lv, f"MTP_DEFINE_ADJ(Lv{lv}, {lv})")),
              (f"mtp_L{lv}_tfw.hip", _unit(lv, f"MTP_DEFINE_ADJ_FWD(Lv{lv}, {lv})"))]
-    for g in range(LEVELS[lv]):
+    for g in range(_ngroups(lv)):
         units.append((f"mtp_L{lv}_rev{g}.hip", _unit(lv, f"MTP_DEFINE_ADJ_REV(Lv{lv}, {lv}, {g})")))
     if lv in FP32_LEVELS:
-        units.append((f"mtp_L{lv}_f32.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, float, f32)")))
+        units.append((f"mtp_L{lv}_f32.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, float, false, f32)")))
     return units
 
 

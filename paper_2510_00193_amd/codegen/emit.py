@@ -49,11 +49,17 @@ class _W:
         return "\n".join(self.lines) + "\n"
 
 
-def entry_groups(prog: Program, n_groups: int):
-    """Split the flat moment layout into n_groups contiguous ranges of similar size."""
+def entry_groups(prog: Program, n_groups):
+    """Split the flat moment layout into contiguous ranges: n_groups ranges of similar size,
+    or, given a tuple, the interior boundaries themselves (e.g. (84,) at level 16 separates the
+    mu = 0 components from the rest)."""
     n = prog.n_mom
-    bounds = [round(k * n / n_groups) for k in range(n_groups + 1)]
-    return [(bounds[k], bounds[k + 1]) for k in range(n_groups)]
+    if isinstance(n_groups, (tuple, list)):
+        bounds = [0] + [int(b) for b in n_groups] + [n]
+        assert all(bounds[k] < bounds[k + 1] for k in range(len(bounds) - 1))
+    else:
+        bounds = [round(k * n / n_groups) for k in range(n_groups + 1)]
+    return [(bounds[k], bounds[k + 1]) for k in range(len(bounds) - 1)]
 
 
 def _ref(r, mvar="me"):
@@ -66,123 +72,113 @@ def _ref(r, mvar="me"):
 
 
 def _emit_pair_functions(w: _W, prog: Program, groups):
+    """Moment accumulation and pair gradient, emitted degree by degree: the monomials of
+    degree nu are formed from those of degree nu - 1 and consumed right away, so only two
+    degrees of monomials are live at once."""
     items = prog.layout.items
-    maxnu = prog.max_nu
-    nmu = prog.n_mu
     for gi, (lo, hi) in enumerate(groups):
         ents = list(range(lo, hi))
-        gnu = max(a + b + c for (_, a, b, c) in (items[e] for e in ents))
+        by_mono = defaultdict(list)
+        for e in ents:
+            mu, a, b, c = items[e]
+            by_mono[(a, b, c)].append((e, mu))
+        gnu = max(a + b + c for (a, b, c) in by_mono)
         # ---------------- moment accumulation
         w(f"// entries [{lo}, {hi}) of the moment layout")
         w("template <class R>")
         w(f"static __device__ __forceinline__ void acc_moments_g{gi}(R* __restrict__ m, const R* __restrict__ f, R x, R y, R z) {{")
         w.push()
-        _emit_powers(w, gnu)
-        by_mono = defaultdict(list)
-        for e in ents:
-            mu, a, b, c = items[e]
-            by_mono[(a, b, c)].append((e, mu))
-        _emit_monomials(w, sorted(by_mono, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])), "mono")
-        for abc in sorted(by_mono, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])):
-            for e, mu in by_mono[abc]:
-                w(f"m[{e - lo}] = fma(f[{mu}], {_mono_name(abc)}, m[{e - lo}]);")
+        need = _monomial_closure(by_mono.keys())
+        for nu in range(gnu + 1):
+            for abc in _degree(need, nu):
+                _emit_one_monomial(w, abc)
+            for abc in _degree(by_mono.keys(), nu):
+                for e, mu in by_mono[abc]:
+                    w(f"m[{e - lo}] = fma(f[{mu}], {_mono_name(abc)}, m[{e - lo}]);")
         w.pop()
         w("}")
-        # ---------------- gradient of the moment contraction with mb
+        # ---------------- gradient of sum_e mb_e f_mu_e mono_e, and u = sum_mu fp_mu S_mu
         w("template <class R>")
         w(f"static __device__ __forceinline__ void pair_grad_g{gi}(const R* __restrict__ mb, const R* __restrict__ f,")
         w("    const R* __restrict__ fp, R x, R y, R z, R& gx, R& gy, R& gz, R& u) {")
         w.push()
-        _emit_powers(w, gnu)
-        need = set()
-        for e in ents:
-            mu, a, b, c = items[e]
-            need.add((a, b, c))
+        lows = set()
+        for (a, b, c) in by_mono:
             if a:
-                need.add((a - 1, b, c))
+                lows.add((a - 1, b, c))
             if b:
-                need.add((a, b - 1, c))
+                lows.add((a, b - 1, c))
             if c:
-                need.add((a, b, c - 1))
-        order = sorted(need, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1]))
-        _emit_monomials(w, order, "mono")
+                lows.add((a, b, c - 1))
+        need = _monomial_closure(set(by_mono.keys()) | lows)
         mus = sorted({items[e][0] for e in ents})
         for mu in mus:
             w(f"R s{mu} = R(0);")
-        by_mono = defaultdict(list)
-        for e in ents:
-            mu, a, b, c = items[e]
-            by_mono[(a, b, c)].append((e, mu))
-        for abc in sorted(by_mono, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1])):
-            lst = by_mono[abc]
-            for e, mu in lst:
-                w(f"s{mu} = fma(mb[{e - lo}], {_mono_name(abc)}, s{mu});")
-            a, b, c = abc
-            if a + b + c == 0:
-                continue
-            # t = sum_mu f_mu mb[mu, abc]
-            first = True
-            for e, mu in lst:
-                if first:
-                    w(f"{{ R t = f[{mu}] * mb[{e - lo}];")
-                    first = False
-                else:
-                    w(f"  t = fma(f[{mu}], mb[{e - lo}], t);")
-            for var, k, low in (("gx", a, (a - 1, b, c)), ("gy", b, (a, b - 1, c)), ("gz", c, (a, b, c - 1))):
-                if k == 0:
+        for nu in range(gnu + 1):
+            for abc in _degree(need, nu):
+                _emit_one_monomial(w, abc)
+            for abc in _degree(by_mono.keys(), nu):
+                lst = by_mono[abc]
+                for e, mu in lst:
+                    w(f"s{mu} = fma(mb[{e - lo}], {_mono_name(abc)}, s{mu});")
+                a, b, c = abc
+                if a + b + c == 0:
                     continue
-                if k == 1:
-                    w(f"  {var} = fma(t, {_mono_name(low)}, {var});")
-                else:
-                    w(f"  {var} = fma(R({k}) * t, {_mono_name(low)}, {var});")
-            w("}")
+                first = True
+                for e, mu in lst:
+                    if first:
+                        w(f"{{ R t = f[{mu}] * mb[{e - lo}];")
+                        first = False
+                    else:
+                        w(f"  t = fma(f[{mu}], mb[{e - lo}], t);")
+                for var, k, low in (("gx", a, (a - 1, b, c)), ("gy", b, (a, b - 1, c)), ("gz", c, (a, b, c - 1))):
+                    if k == 0:
+                        continue
+                    if k == 1:
+                        w(f"  {var} = fma(t, {_mono_name(low)}, {var});")
+                    else:
+                        w(f"  {var} = fma(R({k}) * t, {_mono_name(low)}, {var});")
+                w("}")
         for mu in mus:
             w(f"u = fma(fp[{mu}], s{mu}, u);")
         w.pop()
         w("}")
 
 
+def _degree(keys, nu):
+    return sorted((k for k in keys if k[0] + k[1] + k[2] == nu), key=lambda t: (-t[0], -t[1]))
+
+
+def _monomial_closure(keys):
+    """Every monomial on the construction chain of the given ones (z, then y, then x factors)."""
+    need = set()
+    for a, b, c in keys:
+        for k in range(c + 1):
+            need.add((a, b, k))
+        for k in range(b + 1):
+            need.add((a, k, 0))
+        for k in range(a + 1):
+            need.add((k, 0, 0))
+    return need
+
+
+def _emit_one_monomial(w, abc):
+    """mono_a_b_c from the monomial one factor lower on its chain (z, then y, then x)."""
+    a, b, c = abc
+    name = _mono_name(abc)
+    if a + b + c == 0:
+        w(f"const R {name} = R(1);")
+    elif c > 0:
+        w(f"const R {name} = {_mono_name((a, b, c - 1))} * z;")
+    elif b > 0:
+        w(f"const R {name} = {_mono_name((a, b - 1, 0))} * y;")
+    else:
+        w(f"const R {name} = {_mono_name((a - 1, 0, 0))} * x;")
+
+
 def _mono_name(abc):
     a, b, c = abc
     return f"mono_{a}_{b}_{c}"
-
-
-def _emit_powers(w, nu):
-    for v in "xyz":
-        for k in range(2, nu + 1):
-            prev = v if k == 2 else f"{v}{k - 1}"
-            w(f"const R {v}{k} = {prev} * {v};")
-
-
-def _pw(v, k):
-    if k == 0:
-        return None
-    if k == 1:
-        return v
-    return f"{v}{k}"
-
-
-def _emit_monomials(w, order, _prefix):
-    have = set()
-    for abc in order:
-        a, b, c = abc
-        name = _mono_name(abc)
-        if a + b + c == 0:
-            w(f"const R {name} = R(1);")
-            have.add(abc)
-            continue
-        # reuse a lower monomial times one power when possible
-        done = False
-        for (da, db, dc), var in (((0, 0, 1), "z"), ((0, 1, 0), "y"), ((1, 0, 0), "x")):
-            low = (a - da, b - db, c - dc)
-            if min(low) >= 0 and low in have:
-                w(f"const R {name} = {_mono_name(low)} * {var};")
-                done = True
-                break
-        if not done:
-            parts = [p for p in (_pw("x", a), _pw("y", b), _pw("z", c)) if p]
-            w(f"const R {name} = {' * '.join(parts)};")
-        have.add(abc)
 
 
 def _group_ops(ops):

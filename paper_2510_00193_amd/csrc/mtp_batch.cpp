@@ -125,7 +125,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
                      double* d_shift, hipStream_t s) {
   mtp_model* m = b->m;
   const LevelOps& L = m->ops;
-  const ChainOps& K = L.chain[0];
+  const ChainOps& K = L.chain[2];
   const int n = b->n;
   const long ld = chunk_of(b);
   const long KR = m->nrad;

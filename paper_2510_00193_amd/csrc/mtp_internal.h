@@ -55,7 +55,8 @@ struct AdjOps {
 // Launchers of one compiled level (assembled from the level's translation units).
 struct LevelOps {
   int level, nmom, ncomp, nalpha, nmu, maxnu, ngroup, triples;
-  ChainOps chain[2];  // [0] binary64, [1] binary32 moments (null when not compiled)
+  ChainOps chain[3];  // [0] binary64, [1] binary32 moments (null when not compiled),
+                      // [2] binary64 for batches (per-atom cells, atom permutation, per-atom virials)
   AdjOps adj;
 };
 

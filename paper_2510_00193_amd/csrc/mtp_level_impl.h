@@ -80,7 +80,23 @@ __device__ __forceinline__ void for_pairs(const SysArgs& a, int i, const double*
 }
 
 // ---------------------------------------------------------------------------- moments
-template <class L, int G, class R>
+template <bool BATCH>
+__device__ __forceinline__ int sweep_atom(const SysArgs& a, int k) {
+  if constexpr (BATCH) return atom_at(a, k);
+  else return k;
+}
+// cell of atom i: the kernel-argument copy (uniform, scalar registers) for one system
+template <bool BATCH>
+__device__ __forceinline__ void cell_of(const SysArgs& a, int i, double* H) {
+  if constexpr (BATCH) {
+    load_cell(a, i, H);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) H[k] = a.H[k];
+  }
+}
+
+template <class L, int G, class R, bool BATCH>
 __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
                                                         R* __restrict__ mout, long ld) {
   __shared__ R csh[kMaxRadial];
@@ -88,9 +104,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  const int i = atom_at(a, i0 + li);
+  const int i = sweep_atom<BATCH>(a, i0 + li);
   double H[9];
-  load_cell(a, i, H);
+  cell_of<BATCH>(a, i, H);
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   R m[NG];
 #pragma unroll
@@ -155,7 +171,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_rev(const R* __restrict_
 
 // ---------------------------------------------------------------------------- backward pairs
 // g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials.
-template <class L, int G, class R>
+template <class L, int G, class R, bool BATCH>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
                                                          const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
@@ -169,9 +185,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   double w[6] = {0, 0, 0, 0, 0, 0};
   if (li < n) {
-    const int i = atom_at(a, i0 + li);
+    const int i = sweep_atom<BATCH>(a, i0 + li);
     double H[9];
-    load_cell(a, i, H);
+    cell_of<BATCH>(a, i, H);
     R mb[NG];
 #pragma unroll
     for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li];
@@ -203,7 +219,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
       w[4] -= dx * gz;
       w[5] -= dy * gz;
     });
-    if (watom) {
+    if constexpr (BATCH) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) watom[6L * i + k] = accumulate ? watom[6L * i + k] + w[k] : w[k];
     }
@@ -399,10 +415,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <class L, int G, class R>
+template <class L, int G, class R, bool BATCH>
 void launch_moments_g(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_moments<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  hipLaunchKernelGGL((k_moments<L, G, R, BATCH>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
 }
 template <class L, int G, class R>
 void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s) {
@@ -410,37 +426,37 @@ void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipSt
   hipLaunchKernelGGL((k_program_rev<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, n,
                      (const R*)cb, (R*)mb);
 }
-template <class L, int G, class R>
+template <class L, int G, class R, bool BATCH>
 void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                        int acc, double* wpart, double* watom, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_backward<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (const R*)mb,
+  hipLaunchKernelGGL((k_backward<L, G, R, BATCH>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (const R*)mb,
                      ld, g, acc, wpart, watom);
 }
 
-template <class L, class R, size_t... Gs>
+template <class L, class R, bool BATCH, size_t... Gs>
 void dispatch_moments(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s,
                       std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_moments_g<L, (int)Gs, R>(a, i0, n, m, ld, s) : void()), ...);
+  ((g == (int)Gs ? launch_moments_g<L, (int)Gs, R, BATCH>(a, i0, n, m, ld, s) : void()), ...);
 }
 template <class L, class R, size_t... Gs>
 void dispatch_rev(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s,
                   std::index_sequence<Gs...>) {
   ((g == (int)Gs ? launch_rev_g<L, (int)Gs, R>(m, ld, n, cb, mb, s) : void()), ...);
 }
-template <class L, class R, size_t... Gs>
+template <class L, class R, bool BATCH, size_t... Gs>
 void dispatch_backward(int g, const SysArgs& a, int i0, int n, const void* mb, long ld,
                        double* gout, int acc, double* wpart, double* watom, hipStream_t s,
                        std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R>(a, i0, n, mb, ld, gout, acc, wpart, watom, s)
+  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R, BATCH>(a, i0, n, mb, ld, gout, acc, wpart, watom, s)
                  : void()),
    ...);
 }
 
-template <class L, class R>
+template <class L, class R, bool BATCH>
 struct EnergyChain {
   static void moments(int g, const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
-    dispatch_moments<L, R>(g, a, i0, n, m, ld, s, std::make_index_sequence<L::NGROUP>{});
+    dispatch_moments<L, R, BATCH>(g, a, i0, n, m, ld, s, std::make_index_sequence<L::NGROUP>{});
   }
   static void prog_fwd(const void* m, long ld, int i0, int n, const int* perm, const int* species,
                        const double* xi, const double* shift, int nsp, double* e_atom, void* cbar,
@@ -454,8 +470,8 @@ struct EnergyChain {
   }
   static void backward(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* gout,
                        int acc, double* wpart, double* watom, hipStream_t s) {
-    dispatch_backward<L, R>(grp, a, i0, n, mb, ld, gout, acc, wpart, watom, s,
-                            std::make_index_sequence<L::NGROUP>{});
+    dispatch_backward<L, R, BATCH>(grp, a, i0, n, mb, ld, gout, acc, wpart, watom, s,
+                                   std::make_index_sequence<L::NGROUP>{});
   }
   static ChainOps ops() { return ChainOps{&moments, &prog_fwd, &prog_rev, &backward}; }
 };
@@ -518,9 +534,9 @@ struct AdjImpl {
 
 // One level is compiled as several translation units (binary64 chain, binary32 chain,
 // adjoint, assembly) so that large levels build in parallel.
-#define MTP_DEFINE_CHAIN(LV, NUM, TYPE, TAG) \
-  namespace mtp {                            \
-  ChainOps chain_ops_##NUM##_##TAG() { return EnergyChain<LV, TYPE>::ops(); } \
+#define MTP_DEFINE_CHAIN(LV, NUM, TYPE, BATCH, TAG) \
+  namespace mtp {                                   \
+  ChainOps chain_ops_##NUM##_##TAG() { return EnergyChain<LV, TYPE, BATCH>::ops(); } \
   }
 #define MTP_DEFINE_ADJ(LV, NUM) \
   namespace mtp {               \

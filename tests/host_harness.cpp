@@ -174,6 +174,50 @@ int main() {
     for (int e = 0; e < L::NMOM; ++e) want[e] = (rp[e] - rm[e]) / (2 * h);
     std::printf("rev_tan %.3e\n", relerr(mbd, want));
   }
+  // ---- pair gradient: grad_d of sum_e mb_e f_mu(r) mono_e(d) against central differences
+  {
+    std::vector<double> mb(L::NMOM);
+    for (auto& v : mb) v = unif(-1, 1);
+    auto energy = [&](double x, double y, double z) {
+      double r = std::sqrt(x * x + y * y + z * z), f[L::NMU], fp[L::NMU];
+      radial(r, f, fp);
+      std::vector<double> m(L::NMOM, 0.0);
+      for (int g = 0; g < L::NGROUP; ++g) {
+        double part[L::NMOM] = {0};
+        const int lo = L::GROUP_LO[g];
+        if (g == 0) L::acc_moments<0>(part, f, x, y, z);
+#if MTP_NGROUP > 1
+        if (g == 1) L::acc_moments<1>(part, f, x, y, z);
+#endif
+#if MTP_NGROUP > 2
+        if (g == 2) L::acc_moments<2>(part, f, x, y, z);
+#endif
+        for (int e = lo; e < L::GROUP_HI[g]; ++e) m[e] = part[e - lo];
+      }
+      double e = 0;
+      for (int k = 0; k < L::NMOM; ++k) e += mb[k] * m[k];
+      return e;
+    };
+    double x = d[3], y = d[4], z = d[5];
+    double r = std::sqrt(x * x + y * y + z * z), f[L::NMU], fp[L::NMU];
+    radial(r, f, fp);
+    double gx = 0, gy = 0, gz = 0, u = 0;
+    for (int g = 0; g < L::NGROUP; ++g) {
+      const int lo = L::GROUP_LO[g];
+      if (g == 0) L::pair_grad<0>(mb.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
+#if MTP_NGROUP > 1
+      if (g == 1) L::pair_grad<1>(mb.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
+#endif
+#if MTP_NGROUP > 2
+      if (g == 2) L::pair_grad<2>(mb.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
+#endif
+    }
+    std::vector<double> got = {gx + u * x / r, gy + u * y / r, gz + u * z / r}, want(3);
+    want[0] = (energy(x + h, y, z) - energy(x - h, y, z)) / (2 * h);
+    want[1] = (energy(x, y + h, z) - energy(x, y - h, z)) / (2 * h);
+    want[2] = (energy(x, y, z + h) - energy(x, y, z - h)) / (2 * h);
+    std::printf("pair_grad %.3e\n", relerr(got, want));
+  }
   // ---- adjoint pair sums against the plain definition
   {
     std::vector<double> mb(L::NMOM), mbd(L::NMOM);

@@ -29,6 +29,6 @@ def test_generated_tangents_match_differences(tmp_path, level, groups):
     errs = {line.split()[0]: float(line.split()[1]) for line in out.strip().splitlines()}
     assert errs["fwd_value"] == 0.0
     assert errs["products_cb"] == 0.0
-    for k in ("tan_moments", "fwd_tan", "products_out", "products_cbd", "rev_tan"):
+    for k in ("tan_moments", "fwd_tan", "products_out", "products_cbd", "rev_tan", "pair_grad"):
         assert errs[k] < 1e-7, (k, errs)
     assert errs["adj_pair_S"] < 1e-13 and errs["adj_pair_A"] < 1e-13, errs

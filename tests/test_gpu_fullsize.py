@@ -81,3 +81,24 @@ def test_workload4_sampled_grade():
     g = out["grade"].cpu().numpy()
     assert np.max(np.abs(g[atoms] - g_ref) / np.maximum(1.0, g_ref)) < TOL_GRADE
     assert float(out["grade_max"].cpu()) == pytest.approx(g.max(), rel=0, abs=0)
+
+
+def test_workload2_parameter_gradient_full_size():
+    """VJP of (E, F) at 16,000 atoms against the oracle accumulated over centre chunks."""
+    s, w, pot = _load(2)
+    p = w["params"]
+    rng = np.random.default_rng(222)
+    fbar = rng.normal(size=(s.n_atoms, 3))
+    ebar = 0.37
+    pos = torch.as_tensor(s.pos, device="cuda")
+    sp = torch.as_tensor(s.species, device="cuda")
+    print(f"[vjp full size] N={s.n_atoms}", flush=True)
+    got = pot.param_grad(pos, sp, s.cell, ebar, torch.as_tensor(fbar, device="cuda"))
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy() for x in got]
+    nl = onb.neighbor_csr(s.pos, s.cell, p.r_cut)
+    want = om.param_vjp_chunked(om.Model.from_params(p), s, ebar, fbar, nl, chunk=1000)
+    for name, g, r in zip(("d_linear", "d_radial", "d_shift"), got, want):
+        err = rel_err(g, r)
+        print(f"  {name}: rel err {err:.2e}", flush=True)
+        assert err < 1e-9, name

@@ -303,3 +303,14 @@ def test_sampled_helpers_equal_full_evaluation():
     np.testing.assert_allclose(b, full["B"].detach().numpy()[atoms], rtol=1e-13, atol=1e-300)
     f = om.sampled_forces(model, s, atoms)
     assert _rel(f, full["F"].detach().numpy()[atoms]) < 1e-12
+
+
+def test_chunked_vjp_equals_whole():
+    s, rng = _small_struct(91, n_species=2, n=12)
+    model = _model(10, 2, rng)
+    fbar = rng.normal(size=(s.n_atoms, 3))
+    nl = onb.neighbor_csr(s.pos, s.cell, model.r_cut)
+    whole = om.param_vjp(model, s, 0.6, fbar, nl)
+    parts = om.param_vjp_chunked(model, s, 0.6, fbar, nl, chunk=5)
+    for a, b in zip(whole, parts):
+        assert _rel(b, a) < 1e-12

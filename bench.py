@@ -203,6 +203,8 @@ def main(argv=None):
     ap.add_argument("--rep", type=int, default=80, help="bcc repeat (80 -> 1,024,000 atoms)")
     ap.add_argument("--sections", default="fp32,grade,adjoint,batch",
                     help="extra sections after the headline (comma list, or 'none')")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -226,6 +228,12 @@ def main(argv=None):
     def step():
         return pot.compute(pos, sp, s.cell)
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -10,8 +10,10 @@ prebuilt list, per-kernel times and the roofline of the dominant kernel.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,6 +39,47 @@ def flop_model(info, n_cheb):
         "program_reverse": ("atom", 6 * T),
         "pair_backward": ("pair", 6 * n_cheb + 2 * nmu * n_cheb + 8 * C + 10 * nmu + 22),
     }
+
+
+# sources that determine the per-atom kernels; counters taken on other sources are stale
+KERNEL_SOURCES = ("paper_2510_00193_amd/codegen", "paper_2510_00193_amd/csrc/mtp_level_impl.h",
+                  "paper_2510_00193_amd/csrc/mtp_device.h", "paper_2510_00193_amd/csrc/mtp_internal.h",
+                  "paper_2510_00193_amd/build.py")
+TRAFFIC_FILE = os.path.join("profiles", "hbm_traffic_bcc80_L16.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    files = []
+    for rel in KERNEL_SOURCES:
+        path = os.path.join(ROOT, rel)
+        if os.path.isdir(path):
+            files += sorted(os.path.join(rel, f) for f in os.listdir(path) if f.endswith(".py"))
+        else:
+            files.append(rel)
+    for rel in files:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_class, n_atoms):
+    """HBM bytes per launch of a kernel class from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when the summary is missing,
+    was taken on another workload size, or the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    meta = dict(re.findall(r"^- (\w+): (\S+)", text, re.M))
+    if meta.get("source_hash") != kernel_source_hash() or meta.get("atoms") != str(n_atoms):
+        return None
+    for row in re.findall(r"^\| `?(\w+)`? \|(.*)$", text, re.M):
+        if row[0] == kernel_class:
+            cells = [c.strip() for c in row[1].split("|")]
+            return float(cells[2]) * 1e6   # column "total MB per launch"
+    return None
 
 
 def cpu_baseline(params, target_s=12.0):
@@ -278,7 +321,7 @@ def main(argv=None):
     flops_per_launch = per_unit * units_per_step / kernels[dom]["launches_per_step"]
     achieved = flops_per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom, n), "kernel": dom,
                 "flops_per_unit": per_unit, "unit_of_work": unit, "launch_avg_ms": kernels[dom]["avg_ms"]}
     total_flops = sum(fm[k][1] * (n_pairs if fm[k][0] == "pair" else n) for k in fm)
 

@@ -55,33 +55,37 @@ __device__ __forceinline__ double dist2_exact(double dx, double dy, double dz) {
 
 // Radial functions of one pair: f_mu = w^2 A_mu, f'_mu = w (a w D_mu - 2 A_mu), with
 // A_mu = sum_b c_mu,b T_b(u), D_mu = sum_b c_mu,b T'_b(u), w = r_cut - r, u = a r + b0.
-// c points at c[z_i][z_j][0][0] (n_mu x n_cheb, row-major).
-template <class R, int NMU>
+// c points at c[z_i][z_j][0][0] (n_mu x n_cheb, row-major).  NC > 0 fixes the Chebyshev count
+// at compile time (the recurrence unrolls and the coefficient loads issue together); NC == 0
+// takes it from ncheb.  Both forms perform the same operations in the same order.
+template <class R, int NMU, int NC = 0>
 __device__ __forceinline__ void radial(R r, R sa, R sb, R rcut, const R* __restrict__ c, int ncheb,
                                        R* __restrict__ f, R* __restrict__ fp) {
+  const int nc = NC > 0 ? NC : ncheb;
   const R u = fma(sa, r, sb);
   const R w = rcut - r;
   R A[NMU], D[NMU];
 #pragma unroll
   for (int mu = 0; mu < NMU; ++mu) {
-    A[mu] = c[mu * ncheb];
+    A[mu] = c[mu * nc];
     D[mu] = R(0);
   }
   R t_2 = R(1), t_1 = u, d_2 = R(0), d_1 = R(1);
-  if (ncheb > 1) {
+  if (nc > 1) {
 #pragma unroll
     for (int mu = 0; mu < NMU; ++mu) {
-      A[mu] = fma(c[mu * ncheb + 1], t_1, A[mu]);
-      D[mu] = D[mu] + c[mu * ncheb + 1];
+      A[mu] = fma(c[mu * nc + 1], t_1, A[mu]);
+      D[mu] = D[mu] + c[mu * nc + 1];
     }
   }
-  for (int b = 2; b < ncheb; ++b) {
+#pragma unroll
+  for (int b = 2; b < nc; ++b) {
     const R t = fma(R(2) * u, t_1, -t_2);
     const R d = fma(R(2) * u, d_1, fma(R(2), t_1, -d_2));
 #pragma unroll
     for (int mu = 0; mu < NMU; ++mu) {
-      A[mu] = fma(c[mu * ncheb + b], t, A[mu]);
-      D[mu] = fma(c[mu * ncheb + b], d, D[mu]);
+      A[mu] = fma(c[mu * nc + b], t, A[mu]);
+      D[mu] = fma(c[mu * nc + b], d, D[mu]);
     }
     t_2 = t_1;
     t_1 = t;
@@ -97,23 +101,25 @@ __device__ __forceinline__ void radial(R r, R sa, R sb, R rcut, const R* __restr
 }
 
 // Radial function values only.
-template <class R, int NMU>
+template <class R, int NMU, int NC = 0>
 __device__ __forceinline__ void radial_values(R r, R sa, R sb, R rcut, const R* __restrict__ c,
                                               int ncheb, R* __restrict__ f) {
+  const int nc = NC > 0 ? NC : ncheb;
   const R u = fma(sa, r, sb);
   const R w = rcut - r;
   R A[NMU];
 #pragma unroll
-  for (int mu = 0; mu < NMU; ++mu) A[mu] = c[mu * ncheb];
+  for (int mu = 0; mu < NMU; ++mu) A[mu] = c[mu * nc];
   R t_2 = R(1), t_1 = u;
-  if (ncheb > 1) {
+  if (nc > 1) {
 #pragma unroll
-    for (int mu = 0; mu < NMU; ++mu) A[mu] = fma(c[mu * ncheb + 1], t_1, A[mu]);
+    for (int mu = 0; mu < NMU; ++mu) A[mu] = fma(c[mu * nc + 1], t_1, A[mu]);
   }
-  for (int b = 2; b < ncheb; ++b) {
+#pragma unroll
+  for (int b = 2; b < nc; ++b) {
     const R t = fma(R(2) * u, t_1, -t_2);
 #pragma unroll
-    for (int mu = 0; mu < NMU; ++mu) A[mu] = fma(c[mu * ncheb + b], t, A[mu]);
+    for (int mu = 0; mu < NMU; ++mu) A[mu] = fma(c[mu * nc + b], t, A[mu]);
     t_2 = t_1;
     t_1 = t;
   }

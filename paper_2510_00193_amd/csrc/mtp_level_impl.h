@@ -96,7 +96,7 @@ __device__ __forceinline__ void cell_of(const SysArgs& a, int i, double* H) {
   }
 }
 
-template <class L, int G, class R, bool BATCH>
+template <class L, int G, class R, bool BATCH, int NC>
 __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
                                                         R* __restrict__ mout, long ld) {
   __shared__ R csh[kMaxRadial];
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
   const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
   for_pairs(a, i, H, rix, riy, riz, [&](int, int, int zj, double dx, double dy, double dz, double r) {
     R f[L::NMU];
-    radial_values<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f);
+    radial_values<R, L::NMU, NC>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f);
     L::template acc_moments<G>(m, f, (R)dx, (R)dy, (R)dz);
   });
 #pragma unroll
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_rev(const R* __restrict_
 
 // ---------------------------------------------------------------------------- backward pairs
 // g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials.
-template <class L, int G, class R, bool BATCH>
+template <class L, int G, class R, bool BATCH, int NC>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
                                                          const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
     for_pairs(a, i, H, rix, riy, riz, [&](int p, int, int zj, double dx, double dy, double dz, double r) {
       R f[L::NMU], fp[L::NMU];
-      radial<R, L::NMU>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f, fp);
+      radial<R, L::NMU, NC>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f, fp);
       R rgx = R(0), rgy = R(0), rgz = R(0), ru = R(0);
       L::template pair_grad<G>(mb, f, fp, (R)dx, (R)dy, (R)dz, rgx, rgy, rgz, ru);
       const double ur = (double)ru / r;
@@ -415,10 +415,17 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 }
 
 // ---------------------------------------------------------------------------- launchers
+// The pair kernels come in Chebyshev-count specialisations for the common sizes 8 and 10 and a
+// runtime-count form for the rest.
 template <class L, int G, class R, bool BATCH>
 void launch_moments_g(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_moments<L, G, R, BATCH>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  if (a.ncheb == 8)
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  else if (a.ncheb == 10)
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  else
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
 }
 template <class L, int G, class R>
 void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s) {
@@ -430,8 +437,15 @@ template <class L, int G, class R, bool BATCH>
 void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                        int acc, double* wpart, double* watom, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  hipLaunchKernelGGL((k_backward<L, G, R, BATCH>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (const R*)mb,
-                     ld, g, acc, wpart, watom);
+  if (a.ncheb == 8)
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+                       (const R*)mb, ld, g, acc, wpart, watom);
+  else if (a.ncheb == 10)
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+                       (const R*)mb, ld, g, acc, wpart, watom);
+  else
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+                       (const R*)mb, ld, g, acc, wpart, watom);
 }
 
 template <class L, class R, bool BATCH, size_t... Gs>

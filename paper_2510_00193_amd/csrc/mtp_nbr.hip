@@ -179,6 +179,9 @@ __global__ void k_bin(const double* __restrict__ pos, const int* __restrict__ sp
     atomicAdd(&bincount[0], 1);
     return;
   }
+  // the staged path's distance filter assumes coordinates below 1e7 (its margin covers the
+  // rounding of such magnitudes); larger ones take the unstaged path
+  if (fabs(x) > 1e7 || fabs(y) > 1e7 || fabs(z) > 1e7) flag[3] = 1;
   double f[3];
   frac_of(pos, i, pa.Hinv, f);
   int b[3];
@@ -202,13 +205,28 @@ __global__ void k_bin(const double* __restrict__ pos, const int* __restrict__ sp
   atomicAdd(&bincount[id], 1);
 }
 
+// Image offsets of one atom packed as three biased bytes (|offset| <= 60 by the binning check).
+__device__ __forceinline__ int pack_img(int o0, int o1, int o2) {
+  return ((o0 + 128) << 16) | ((o1 + 128) << 8) | (o2 + 128);
+}
+
+// Bin contents: atom index, and (for the staged path) binned copies of the position and of the
+// packed image offsets, so that a bin's atoms are contiguous in memory.
 __global__ void k_bin_scatter(int n, const int* __restrict__ bin, const int* __restrict__ binstart,
-                              int* __restrict__ binfill, int* __restrict__ binatoms) {
+                              int* __restrict__ binfill, int* __restrict__ binatoms,
+                              const double* __restrict__ pos, const int* __restrict__ img,
+                              double* __restrict__ binpos, int* __restrict__ binimg) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int id = bin[i];
-  const int slot = atomicAdd(&binfill[id], 1);
-  binatoms[binstart[id] + slot] = i;
+  const int q = binstart[id] + atomicAdd(&binfill[id], 1);
+  binatoms[q] = i;
+  if (binpos) {
+    binpos[3L * q] = pos[3 * i];
+    binpos[3L * q + 1] = pos[3 * i + 1];
+    binpos[3L * q + 2] = pos[3 * i + 2];
+    binimg[q] = pack_img(img[3 * i], img[3 * i + 1], img[3 * i + 2]);
+  }
 }
 
 template <bool FILL>
@@ -334,102 +352,176 @@ __global__ void k_rev(long long total, const int* __restrict__ off, const int* _
 }
 
 // ---------------------------------------------------------------- cell path, one workgroup per bin
-// The workgroup stages the candidates of the 27 surrounding bins in LDS once (positions,
-// indices and the image offset each candidate needs), then each wave takes one centre atom of
-// the bin: lanes test candidates, hits are compacted with a ballot into a per-wave LDS list,
-// rank-sorted by key and written as a fixed-capacity row (rows[i * cap + k]).
+// The workgroup stages the candidates of the 27 surrounding bins in LDS once: for each, its
+// position shifted by the image the bin wrap implies (for a distance filter), the key base
+// (j, wrap - image of j) and its slot in the binned arrays.  Each wave then takes one centre
+// atom of the bin:
+//   1. filter: lanes test all candidates with the shifted positions against r_cut^2 plus a
+//      margin that covers the rounding difference to the exact expression (coordinates below
+//      1e7, checked by k_bin), and compact the survivors with a ballot;
+//   2. exact: the survivors are tested with the canonical binary64 expression of
+//      pair_displacement/dist2_exact; hits are compacted into a per-wave LDS list,
+//      rank-sorted by key and written as a fixed-capacity row (rows[i * cap + k]).
+// MAXC and ROWCAP bound the staged candidates and the hits per centre; the host picks the
+// smallest instance that the density allows (LDS per workgroup sets how many workgroups share
+// a CU).  A neighbourhood beyond them, or flag[3] already raised, makes the caller take the
+// unstaged path.
 constexpr int kBinThreads = 256;
 constexpr int kBinWaves = kBinThreads / 64;
-constexpr int kMaxCand = 1024;     // candidates staged per bin neighbourhood
-constexpr int kRowCap = 256;       // hits kept per centre in LDS
+constexpr double kFilterMargin = 1e-6;   // relative slack of the filter on r_cut^2
 
-__global__ __launch_bounds__(kBinThreads) void k_bin_rows(const double* __restrict__ pos, PlanArgs pa,
-                                                          const int* __restrict__ img,
-                                                          const int* __restrict__ binstart,
-                                                          const int* __restrict__ binatoms, int cap,
+__device__ __forceinline__ void shift_vec(int n1, int n2, int n3, const double* H, double& tx, double& ty,
+                                          double& tz) {
+  const double f1 = (double)n1, f2 = (double)n2, f3 = (double)n3;
+  tx = (f1 * H[0] + f2 * H[3]) + f3 * H[6];
+  ty = (f1 * H[1] + f2 * H[4]) + f3 * H[7];
+  tz = (f1 * H[2] + f2 * H[5]) + f3 * H[8];
+}
+
+template <int MAXC, int ROWCAP>
+__global__ __launch_bounds__(kBinThreads) void k_bin_rows(PlanArgs pa, const int* __restrict__ binstart,
+                                                          const int* __restrict__ binatoms,
+                                                          const double* __restrict__ binpos,
+                                                          const int* __restrict__ binimg, int cap,
                                                           long long* __restrict__ rows,
                                                           int* __restrict__ counts, int* __restrict__ flag) {
-  __shared__ double cx[kMaxCand], cy[kMaxCand], cz[kMaxCand];
-  __shared__ int cj[kMaxCand], cb0[kMaxCand], cb1[kMaxCand], cb2[kMaxCand];
-  __shared__ long long hits[kBinWaves][kRowCap];
-  __shared__ int bst[27], boff[28], bw0[27], bw1[27], bw2[27];
+  constexpr int kSurv = 2 * ROWCAP;  // filter survivors kept per centre
+  __shared__ double px[MAXC], py[MAXC], pz[MAXC];
+  __shared__ long long ckey[MAXC];
+  __shared__ int cslot[MAXC];
+  __shared__ long long hits[kBinWaves][ROWCAP];
+  __shared__ unsigned short surv[kBinWaves][kSurv];
+  __shared__ int bst[27], boff[28], bwrap[27];
+  __shared__ int skip;
   const int bid = blockIdx.x;
   const int b2 = bid % pa.nb[2];
   const int b1 = (bid / pa.nb[2]) % pa.nb[1];
   const int b0 = bid / (pa.nb[2] * pa.nb[1]);
-  // the 27 surrounding bins (fixed order) and the wrap each one implies
-  if (threadIdx.x < 27) {
+  // the 27 surrounding bins (fixed order), the wrap each one implies, and their offsets in the
+  // staged list (inclusive scan across the first wave)
+  if (threadIdx.x < 64) {
     const int nbk = threadIdx.x;
-    const int d0 = nbk / 9 - 1, d1 = (nbk / 3) % 3 - 1, d2 = nbk % 3 - 1;
-    int c0 = b0 + d0, w0 = 0, c1 = b1 + d1, w1 = 0, c2 = b2 + d2, w2 = 0;
-    if (c0 < 0) { c0 += pa.nb[0]; w0 = -1; } else if (c0 >= pa.nb[0]) { c0 -= pa.nb[0]; w0 = 1; }
-    if (c1 < 0) { c1 += pa.nb[1]; w1 = -1; } else if (c1 >= pa.nb[1]) { c1 -= pa.nb[1]; w1 = 1; }
-    if (c2 < 0) { c2 += pa.nb[2]; w2 = -1; } else if (c2 >= pa.nb[2]) { c2 -= pa.nb[2]; w2 = 1; }
-    const int cid = (c0 * pa.nb[1] + c1) * pa.nb[2] + c2;
-    bst[nbk] = binstart[cid];
-    boff[nbk + 1] = binstart[cid + 1] - binstart[cid];
-    bw0[nbk] = w0;
-    bw1[nbk] = w1;
-    bw2[nbk] = w2;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    boff[0] = 0;
-    for (int k = 0; k < 27; ++k) boff[k + 1] += boff[k];
+    int cnt = 0;
+    if (nbk < 27) {
+      const int d0 = nbk / 9 - 1, d1 = (nbk / 3) % 3 - 1, d2 = nbk % 3 - 1;
+      int c0 = b0 + d0, w0 = 0, c1 = b1 + d1, w1 = 0, c2 = b2 + d2, w2 = 0;
+      if (c0 < 0) { c0 += pa.nb[0]; w0 = -1; } else if (c0 >= pa.nb[0]) { c0 -= pa.nb[0]; w0 = 1; }
+      if (c1 < 0) { c1 += pa.nb[1]; w1 = -1; } else if (c1 >= pa.nb[1]) { c1 -= pa.nb[1]; w1 = 1; }
+      if (c2 < 0) { c2 += pa.nb[2]; w2 = -1; } else if (c2 >= pa.nb[2]) { c2 -= pa.nb[2]; w2 = 1; }
+      const int cid = (c0 * pa.nb[1] + c1) * pa.nb[2] + c2;
+      bst[nbk] = binstart[cid];
+      cnt = binstart[cid + 1] - binstart[cid];
+      bwrap[nbk] = pack_img(w0, w1, w2);
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const int v = __shfl_up(incl, d, 64);
+      if (nbk >= d) incl += v;
+    }
+    if (nbk < 27) boff[nbk + 1] = incl;
+    if (nbk == 0) {
+      boff[0] = 0;
+      skip = flag[3];  // one read for the whole workgroup: the caller already falls back
+    }
   }
   __syncthreads();
   const int ncand = boff[27];
-  if (ncand > kMaxCand) {
-    if (threadIdx.x == 0) flag[3] = 1;  // too dense for the staged path: caller falls back
+  if (skip) return;
+  if (ncand > MAXC) {
+    if (threadIdx.x == 0) flag[3] = 1;
     return;
   }
   for (int k = threadIdx.x; k < ncand; k += kBinThreads) {
-    int t = 0;
-    while (boff[t + 1] <= k) ++t;
-    const int j = binatoms[bst[t] + (k - boff[t])];
-    cx[k] = pos[3 * j];
-    cy[k] = pos[3 * j + 1];
-    cz[k] = pos[3 * j + 2];
-    cj[k] = j;
-    cb0[k] = bw0[t] - img[3 * j];
-    cb1[k] = bw1[t] - img[3 * j + 1];
-    cb2[k] = bw2[t] - img[3 * j + 2];
+    int lo = 0, hi = 26;  // bin t with boff[t] <= k < boff[t + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const int q = bst[lo] + (k - boff[lo]);
+    const int j = binatoms[q];
+    // wrap - image of j, per axis (both biased bytes)
+    const int wr = bwrap[lo], im = binimg[q];
+    const int c0 = ((wr >> 16) & 0xFF) - ((im >> 16) & 0xFF);
+    const int c1 = ((wr >> 8) & 0xFF) - ((im >> 8) & 0xFF);
+    const int c2 = (wr & 0xFF) - (im & 0xFF);
+    double tx, ty, tz;
+    shift_vec(c0, c1, c2, pa.H, tx, ty, tz);
+    px[k] = binpos[3L * q] + tx;
+    py[k] = binpos[3L * q + 1] + ty;
+    pz[k] = binpos[3L * q + 2] + tz;
+    ckey[k] = make_key(j, c0, c1, c2);
+    cslot[k] = q;
   }
   __syncthreads();
+  const double rc2f = pa.rc2 * (1.0 + kFilterMargin) + kFilterMargin;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
   const int a0 = binstart[bid], a1 = binstart[bid + 1];
   long long* hw = hits[wave];
+  unsigned short* sw = surv[wave];
   for (int ci = a0 + wave; ci < a1; ci += kBinWaves) {
     const int i = binatoms[ci];
-    const double rix = pos[3 * i], riy = pos[3 * i + 1], riz = pos[3 * i + 2];
-    const int oi0 = img[3 * i], oi1 = img[3 * i + 1], oi2 = img[3 * i + 2];
-    int cnt = 0;
+    const double rix = binpos[3L * ci], riy = binpos[3L * ci + 1], riz = binpos[3L * ci + 2];
+    const int im = binimg[ci];
+    const int oi0 = ((im >> 16) & 0xFF) - 128, oi1 = ((im >> 8) & 0xFF) - 128, oi2 = (im & 0xFF) - 128;
+    double ox, oy, oz;
+    shift_vec(oi0, oi1, oi2, pa.H, ox, oy, oz);
+    const double qx = rix - ox, qy = riy - oy, qz = riz - oz;
+    // 1. filter
+    int ns = 0;
     for (int q0 = 0; q0 < ncand; q0 += 64) {
       const int q = q0 + lane;
+      bool pass = false;
+      if (q < ncand) {
+        const double ex = px[q] - qx, ey = py[q] - qy, ez = pz[q] - qz;
+        pass = fma(ez, ez, fma(ey, ey, ex * ex)) < rc2f;
+      }
+      const unsigned long long mask = __ballot(pass);
+      if (pass) {
+        const int slot = ns + __popcll(mask & below);
+        if (slot < kSurv) sw[slot] = (unsigned short)q;
+      }
+      ns += __popcll(mask);
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    if (ns > kSurv) {
+      if (lane == 0) flag[3] = 1;
+      continue;
+    }
+    // 2. exact test of the survivors
+    const long long self = make_key(i, 0, 0, 0);
+    const long long koff = ((long long)oi0 << 16) + ((long long)oi1 << 8) + (long long)oi2;
+    int cnt = 0;
+    for (int h0 = 0; h0 < ns; h0 += 64) {
+      const int h = h0 + lane;
       bool hit = false;
       long long key = 0;
-      if (q < ncand) {
-        const int j = cj[q];
-        const int n1 = cb0[q] + oi0, n2 = cb1[q] + oi1, n3 = cb2[q] + oi2;
-        if (!(j == i && n1 == 0 && n2 == 0 && n3 == 0)) {
+      if (h < ns) {
+        const int q = sw[h];
+        key = ckey[q] + koff;
+        if (key != self) {
+          const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
+                    n3 = (int)(key & 0xFF) - 128;
+          const long sq = cslot[q];
           double dx, dy, dz;
-          pair_displacement(rix, riy, riz, cx[q], cy[q], cz[q], n1, n2, n3, pa.H, dx, dy, dz);
+          pair_displacement(rix, riy, riz, binpos[3 * sq], binpos[3 * sq + 1], binpos[3 * sq + 2], n1, n2, n3,
+                            pa.H, dx, dy, dz);
           hit = dist2_exact(dx, dy, dz) < pa.rc2;
-          key = make_key(j, n1, n2, n3);
         }
       }
       const unsigned long long mask = __ballot(hit);
       if (hit) {
-        const int slot = cnt + __popcll(mask & ((1ull << lane) - 1ull));
-        if (slot < kRowCap) hw[slot] = key;
+        const int slot = cnt + __popcll(mask & below);
+        if (slot < ROWCAP) hw[slot] = key;
       }
       cnt += __popcll(mask);
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    if (cnt > cap || cnt > kRowCap) {
+    if (cnt > cap || cnt > ROWCAP) {
       if (lane == 0) flag[3] = 1;
-      if (lane == 0) counts[i] = 0;
       continue;
     }
     for (int h = lane; h < cnt; h += 64) {
@@ -444,25 +536,30 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(const double* __restri
   }
 }
 
-// CSR from the fixed-capacity rows: one wave per atom copies its sorted row and finds the
-// mirror (j, i, -n) of every pair by binary search in row j.
+// CSR from the fixed-capacity rows: 32 lanes per atom copy its sorted row.  The mirror of a
+// pair (i, j, n) is (j, i, -n); the lane of the pair that owns the unordered pair (j > i, or
+// j == i and the larger packed shift) finds the mirror by binary search in row j and writes
+// rev for both entries, so every unordered pair is searched once.  The list is exactly
+// symmetric (the mirrored displacement is the exact negative), so every mirror exists.
 __global__ __launch_bounds__(256) void k_rows_to_csr(int n, int cap, const long long* __restrict__ rows,
                                                      const int* __restrict__ counts,
                                                      const int* __restrict__ off, int* __restrict__ nj,
                                                      int* __restrict__ shift, int* __restrict__ rev) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int lane = threadIdx.x & 31;
   if (i >= n) return;
   const int cnt = counts[i], o = off[i];
-  for (int k = lane; k < cnt; k += 64) {
+  for (int k = lane; k < cnt; k += 32) {
     const long long key = rows[(long)i * cap + k];
     const int j = (int)(key >> 24);
     const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
               n3 = (int)(key & 0xFF) - 128;
     nj[o + k] = j;
     shift[o + k] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
-    if (rev) {
-      const long long want = make_key(i, -n1, -n2, -n3);
+    const long long sk = key & 0xFFFFFF;
+    const long long want = make_key(i, -n1, -n2, -n3);
+    const bool owner = j > i || (j == i && sk > (want & 0xFFFFFF));
+    if (rev && owner) {
       const long long* rj = rows + (long)j * cap;
       int lo = 0, hi = counts[j] - 1, found = -1;
       while (lo <= hi) {
@@ -474,7 +571,13 @@ __global__ __launch_bounds__(256) void k_rows_to_csr(int n, int cap, const long 
         }
         if (v < want) lo = mid + 1; else hi = mid - 1;
       }
-      rev[o + k] = found < 0 ? -1 : off[j] + found;
+      if (found >= 0) {
+        const int q = off[j] + found;
+        rev[o + k] = q;
+        rev[q] = o + k;
+      } else {
+        rev[o + k] = -1;
+      }
     }
   }
 }
@@ -511,16 +614,31 @@ __global__ void k_scan_local(const int* __restrict__ in, int n, int* __restrict_
   if (threadIdx.x == kNT - 1) bsum[blockIdx.x] = sh[kNT - 1];
 }
 
-__global__ void k_scan_blocks(long long* __restrict__ bsum, int nb, long long* __restrict__ total) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    long long run = 0;
-    for (int b = 0; b < nb; ++b) {
-      const long long t = bsum[b];
-      bsum[b] = run;
-      run += t;
-    }
-    total[0] = run;
+// exclusive scan of the block sums by one workgroup: each thread scans a contiguous run,
+// then the run totals are scanned in LDS
+constexpr int kScanTop = 1024;
+__global__ __launch_bounds__(kScanTop) void k_scan_blocks(long long* __restrict__ bsum, int nb,
+                                                          long long* __restrict__ total) {
+  __shared__ long long sh[kScanTop];
+  const int per = (nb + kScanTop - 1) / kScanTop;
+  const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+  long long acc = 0;
+  for (int b = b0; b < b1; ++b) acc += bsum[b];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 1; s < kScanTop; s <<= 1) {
+    const long long t = threadIdx.x >= s ? sh[threadIdx.x - s] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
   }
+  long long run = sh[threadIdx.x] - acc;
+  for (int b = b0; b < b1; ++b) {
+    const long long t = bsum[b];
+    bsum[b] = run;
+    run += t;
+  }
+  if (threadIdx.x == kScanTop - 1) total[0] = sh[kScanTop - 1];
 }
 
 __global__ void k_scan_add(int* __restrict__ out, int n, const long long* __restrict__ bsum,
@@ -534,13 +652,8 @@ __global__ void k_scan_add(int* __restrict__ out, int n, const long long* __rest
 
 // ---------------------------------------------------------------- workspace
 struct NbrWork {
-  std::vector<void*> bufs;
-  size_t cap[16] = {0};
-  void* ptr[16] = {nullptr};
-  ~NbrWork() {
-    for (int k = 0; k < 16; ++k)
-      if (ptr[k]) (void)hipFree(ptr[k]);
-  }
+  size_t cap[20] = {0};
+  void* ptr[20] = {nullptr};
   template <class T>
   T* get(int slot, size_t n) {
     const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
@@ -553,15 +666,30 @@ struct NbrWork {
     }
     return (T*)ptr[slot];
   }
+  // pinned host words for the one readback of a build: [0] pair total, [1..4] flags
+  long long* host = nullptr;
+  long long* host_words() {
+    if (!host && hipHostMalloc((void**)&host, 8 * sizeof(long long), hipHostMallocDefault) != hipSuccess)
+      host = nullptr;
+    return host;
+  }
+  ~NbrWork();
   PlanArgs pa;
   int row_cap = 0;      // capacity of the staged rows when the workgroup-per-bin path filled them
 };
+
+NbrWork::~NbrWork() {
+  for (int k = 0; k < 20; ++k)
+    if (ptr[k]) (void)hipFree(ptr[k]);
+  if (host) (void)hipHostFree(host);
+}
 
 NbrWork* nbr_work_create() { return new NbrWork(); }
 void nbr_work_destroy(NbrWork* w) { delete w; }
 
 enum Slot { S_FRAC, S_BIN, S_IMG, S_BINCNT, S_BINSTART, S_BINFILL, S_BINATOMS, S_COUNTS, S_BSUM,
-            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG, S_ROWS };
+            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG, S_ROWS, S_BINPOS, S_BINIMG, S_NSLOTS };
+static_assert(S_NSLOTS <= 20, "workspace slots");
 
 static void inv3(const double* H, double* I, double* det) {
   const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7],
@@ -622,7 +750,7 @@ static int scan_counts(NbrWork* w, const int* counts, int n, int* off, long long
   if (!bsum || !tot) return MTP_ERR_OOM;
   if (n > 0) {
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kNT), 0, s, counts, n, off, bsum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1), 0, s, bsum, nb, tot);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanTop), 0, s, bsum, nb, tot);
     hipLaunchKernelGGL(k_scan_add, dim3((n + kNT - 1) / kNT), dim3(kNT), 0, s, off, n, bsum, tot, 1);
   } else {
     (void)hipMemsetAsync(off, 0, sizeof(int), s);
@@ -633,6 +761,22 @@ static int scan_counts(NbrWork* w, const int* counts, int n, int* off, long long
       return MTP_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
   }
+  return 0;
+}
+
+// One readback per pass: the pair total written by scan_counts and the four flags, through
+// pinned host words, then a single stream synchronization.
+static int read_back(NbrWork* w, const int* flag, long long* total, int* flags, hipStream_t s) {
+  long long* h = w->host_words();
+  const long long* tot = w->get<long long>(S_TOTAL, 1);
+  if (!h || !tot) return MTP_ERR_OOM;
+  if (hipMemcpyAsync(h, tot, sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(h + 1, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return MTP_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
+  *total = h[0];
+  const int* f = (const int*)(h + 1);
+  for (int k = 0; k < 4; ++k) flags[k] = f[k];
   return 0;
 }
 
@@ -661,30 +805,41 @@ int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int ns
                          flag);
     int rc = scan_counts(w, bincnt, nbins, binstart, nullptr, s);
     if (rc) return rc;
-    if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(kNT), 0, s, n, bin, binstart, binfill, binatoms);
+    // rows of the staged path, sized from the density (a sphere of radius r_cut, 50% slack),
+    // and the staged candidates from the atoms per bin (27 bins, 50% slack)
     w->row_cap = 0;
+    int inst = 0, cap = 0;
     if (n > 0) {
-      // rows of the staged path, sized from the density (a sphere of radius r_cut, 50% slack)
-      double vol = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
-                        H[2] * (H[3] * H[7] - H[4] * H[6]));
+      const double vol = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                              H[2] * (H[3] * H[7] - H[4] * H[6]));
       const double expect = 4.18879020478639 * rcut * rcut * rcut * n / vol;
-      int cap = (int)(1.5 * expect) + 32;
+      cap = (int)(1.5 * expect) + 32;
       cap = ((cap + 31) / 32) * 32;
-      if (cap <= kRowCap) {
-        long long* rows = w->get<long long>(S_ROWS, (size_t)n * cap);
-        if (!rows) return MTP_ERR_OOM;
-        hipLaunchKernelGGL(k_bin_rows, dim3(nbins), dim3(kBinThreads), 0, s, pos, pa, img, binstart, binatoms,
-                           cap, rows, counts, flag);
-        int fl[4];
-        if (hipMemcpyAsync(fl, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return MTP_ERR_HIP;
-        if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
-        if (fl[3] == 0) w->row_cap = cap;
-        else (void)hipMemsetAsync(flag + 3, 0, sizeof(int), s);
-      }
-      if (w->row_cap == 0)
-        hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart,
-                           binatoms, counts);
+      const double cand = 1.5 * 27.0 * n / nbins + 32;
+      if (cap <= 128 && cand <= 512) inst = 1;
+      else if (cap <= 128 && cand <= 768) inst = 2;
+      else if (cap <= 256 && cand <= 1024) inst = 3;
     }
+    double* binpos = inst ? w->get<double>(S_BINPOS, 3L * n) : nullptr;
+    int* binimg = inst ? w->get<int>(S_BINIMG, n) : nullptr;
+    long long* rows = inst ? w->get<long long>(S_ROWS, (size_t)n * cap) : nullptr;
+    if (inst && (!binpos || !binimg || !rows)) return MTP_ERR_OOM;
+    if (n > 0)
+      hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(kNT), 0, s, n, bin, binstart, binfill, binatoms, pos, img,
+                         binpos, binimg);
+    if (inst == 1)
+      hipLaunchKernelGGL((k_bin_rows<512, 128>), dim3(nbins), dim3(kBinThreads), 0, s, pa, binstart, binatoms,
+                         binpos, binimg, cap, rows, counts, flag);
+    else if (inst == 2)
+      hipLaunchKernelGGL((k_bin_rows<768, 128>), dim3(nbins), dim3(kBinThreads), 0, s, pa, binstart, binatoms,
+                         binpos, binimg, cap, rows, counts, flag);
+    else if (inst == 3)
+      hipLaunchKernelGGL((k_bin_rows<1024, 256>), dim3(nbins), dim3(kBinThreads), 0, s, pa, binstart, binatoms,
+                         binpos, binimg, cap, rows, counts, flag);
+    else if (n > 0)
+      hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart, binatoms,
+                         counts);
+    if (inst) w->row_cap = cap;
   } else {
     double* sfrac = w->get<double>(S_FRAC, 3L * n);
     if (!sfrac) return MTP_ERR_OOM;
@@ -693,11 +848,23 @@ int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int ns
       hipLaunchKernelGGL(k_image_count, dim3(gb), dim3(kNT), 0, s, pos, sfrac, n, pa, counts, flag);
     }
   }
-  int rc = scan_counts(w, counts, n, off, total, s);
+  int rc = scan_counts(w, counts, n, off, nullptr, s);
   if (rc) return rc;
-  if (hipMemcpyAsync(flags, flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return MTP_ERR_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return MTP_ERR_HIP;
+  rc = read_back(w, flag, total, flags, s);
+  if (rc) return rc;
+  if (w->row_cap > 0 && flags[3]) {
+    // a neighbourhood exceeded the staged capacities: count again without staging
+    w->row_cap = 0;
+    (void)hipMemsetAsync(flag + 3, 0, sizeof(int), s);
+    hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, w->get<int>(S_BIN, n),
+                       w->get<int>(S_IMG, 3L * n), w->get<int>(S_BINSTART, 1), w->get<int>(S_BINATOMS, n),
+                       counts);
+    rc = scan_counts(w, counts, n, off, nullptr, s);
+    if (rc) return rc;
+    rc = read_back(w, flag, total, flags, s);
+    if (rc) return rc;
+  }
+  flags[3] = 0;
   return 0;
 }
 

@@ -138,3 +138,30 @@ def test_error_paths():
     with pytest.raises(MtpError) as ei:
         pot.neighbors(pos, sp, s.cell, cap=5)
     assert ei.value.code == 3
+
+
+@pytest.mark.parametrize("n_cheb", [1, 2, 5, 10])
+def test_chebyshev_counts(n_cheb):
+    """Compile-time (8, 10) and runtime Chebyshev counts of the pair kernels."""
+    s, p = small_lattice(808 + n_cheb, (4, 4, 4), 3.16, 0.1, 10, 2, n_cheb=n_cheb)
+    _full_parity(s, p, f"cheb-{n_cheb}")
+
+
+@pytest.mark.parametrize("a,rep,r_cut", [(3.16, 10, 5.0), (3.6, 8, 5.0), (3.0, 7, 5.0), (2.2, 5, 5.0)])
+def test_cell_list_densities(a, rep, r_cut):
+    """Neighbour lists at densities that select each staged capacity of the cell path and the
+    unstaged fallback (bcc 3.16: 512 candidates; fcc 3.6: 768; fcc 3.0: 1024 with 256-entry
+    rows; fcc 2.2: unstaged)."""
+    rng = np.random.default_rng(909)
+    sites, cell = wl.fcc_sites(rep, rep, rep, a) if a != 3.16 else wl.bcc_sites(rep, rep, rep, a)
+    pos = wl.jitter_wrap(sites, cell, 0.05, rng)
+    pos[::5] -= cell[1]   # some atoms one image outside the box
+    s = wl.Structure(pos, np.zeros(len(pos), np.int32), cell)
+    p = wl.draw_params(rng, 10, 1, 3, 8, 17, 2.0, r_cut)
+    print(f"[density a={a} rep={rep} rc={r_cut}] N={s.n_atoms}", flush=True)
+    ref = onb.neighbor_csr(s.pos, s.cell, r_cut)
+    pot = _pot(p)
+    d_pos, d_sp = _dev(s)
+    nl = pot.neighbors(d_pos, d_sp, s.cell)
+    torch.cuda.synchronize()
+    _check_nlist(nl, ref)

@@ -37,6 +37,7 @@ def flop_model(info, n_cheb):
         "moments": ("pair", 3 * n_cheb + 2 * nmu * n_cheb + mono + 2 * C),
         "program_forward": ("atom", 3 * T + 2 * nalpha),
         "program_reverse": ("atom", 6 * T),
+        "program": ("atom", 9 * T + 2 * nalpha),   # forward + reverse fused
         "pair_backward": ("pair", 6 * n_cheb + 2 * nmu * n_cheb + 8 * C + 10 * nmu + 22),
     }
 
@@ -323,7 +324,8 @@ def main(argv=None):
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom, n), "kernel": dom,
                 "flops_per_unit": per_unit, "unit_of_work": unit, "launch_avg_ms": kernels[dom]["avg_ms"]}
-    total_flops = sum(fm[k][1] * (n_pairs if fm[k][0] == "pair" else n) for k in fm)
+    # algorithmic flops of one evaluation: the kernel classes that ran
+    total_flops = sum(fm[k][1] * (n_pairs if fm[k][0] == "pair" else n) for k in fm if k in kernels)
 
     out = {
         "metric": METRIC,

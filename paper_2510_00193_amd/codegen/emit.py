@@ -234,8 +234,9 @@ def _emit_components_forward(w: _W, prog: Program):
 
 def _emit_components_reverse(w: _W, prog: Program, groups):
     for gi, (lo, hi) in enumerate(groups):
-        w("template <class R, class MA>")
-        w(f"static __device__ __forceinline__ void rev_g{gi}(const MA& M, const R* __restrict__ Cb, R* __restrict__ mb) {{")
+        # Cb: anything indexable by component (a pointer, or a strided accessor of LDS)
+        w("template <class R, class MA, class CB>")
+        w(f"static __device__ __forceinline__ void rev_g{gi}(const MA& M, const CB& Cb, R* __restrict__ mb) {{")
         w.push()
         for blk in prog.blocks:
             if not any(lo <= e < hi for e in blk.entries):
@@ -358,7 +359,7 @@ def _emit_dispatchers(w: _W, n_groups: int):
         ("acc_moments", "R* __restrict__ m, const R* __restrict__ f, R x, R y, R z", "m, f, x, y, z", "class R"),
         ("pair_grad", "const R* __restrict__ mb, const R* __restrict__ f, const R* __restrict__ fp, R x, R y, R z, "
                       "R& gx, R& gy, R& gz, R& u", "mb, f, fp, x, y, z, gx, gy, gz, u", "class R"),
-        ("rev", "const MA& M, const R* __restrict__ Cb, R* __restrict__ mb", "M, Cb, mb", "class R, class MA"),
+        ("rev", "const MA& M, const CB& Cb, R* __restrict__ mb", "M, Cb, mb", "class R, class MA, class CB"),
     )
     for name, params, args, tparams in sigs:
         w(f"template <int G, {tparams}>")
@@ -366,7 +367,7 @@ def _emit_dispatchers(w: _W, n_groups: int):
         w.push()
         for g in range(n_groups):
             kw = "if constexpr" if g == 0 else "else if constexpr"
-            targs = "<R>" if name != "rev" else "<R, MA>"
+            targs = "<R>" if name != "rev" else "<R, MA, CB>"
             w(f"{kw} (G == {g}) {name}_g{g}{targs}({args});")
         w.pop()
         w("}")

@@ -104,7 +104,7 @@ ProfScope::~ProfScope() {
 static const char* kProfNames[P_NCLASS] = {"neighbor_build", "moments", "program_forward",
                                            "program_reverse", "pair_backward", "force_gather",
                                            "reductions", "grade_gemm", "tangent", "adjoint_pairs",
-                                           "batch"};
+                                           "batch", "program"};
 
 extern "C" {
 
@@ -383,6 +383,20 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
     for (int g = 0; g < L.ngroup; ++g) {
       ProfScope ps(&m->prof, P_MOMENTS, s);
       K.moments(g, a, i0, cn, mom, ld, s);
+    }
+    if (backward && K.program && !bvals && !after_forward) {
+      // energies and moment adjoints in one kernel
+      {
+        ProfScope ps(&m->prof, P_PROGRAM, s);
+        K.program(mom, ld, i0, cn, sys->species, (const double*)m->linear.p, (const double*)m->shift.p, m->nsp,
+                  e_atom, mbar, s);
+      }
+      {
+        ProfScope ps(&m->prof, P_BACKWARD, s);
+        K.backward(0, a, i0, cn, mbar, ld, (double*)m->g.p, 0, (double*)m->wpart.p + 6 * blk, nullptr, s);
+      }
+      blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
+      continue;
     }
     {
       ProfScope ps(&m->prof, P_PROG_FWD, s);

@@ -26,7 +26,7 @@ struct DevBuf {
 
 // Kernel classes timed by the profiler.
 enum ProfClass { P_NBR = 0, P_MOMENTS, P_PROG_FWD, P_PROG_REV, P_BACKWARD, P_GATHER, P_REDUCE, P_GRADE,
-                 P_TANGENT, P_ADJ_PAIRS, P_BATCH, P_NCLASS };
+                 P_TANGENT, P_ADJ_PAIRS, P_BATCH, P_PROGRAM, P_NCLASS };
 
 struct Profiler {
   bool on = false;

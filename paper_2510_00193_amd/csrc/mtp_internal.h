@@ -37,6 +37,10 @@ struct ChainOps {
   void (*prog_rev)(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s);
   void (*backward)(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                    int acc, double* wpart, double* watom, hipStream_t s);
+  // forward + products + reverse in one kernel (single-group levels, one system; else null):
+  // writes e_atom[i0 + k] and the moment adjoints
+  void (*program)(const void* m, long ld, int i0, int n, const int* species, const double* xi,
+                  const double* shift, int nsp, double* e_atom, void* mb, hipStream_t s);
 };
 
 // Parameter-adjoint launchers of one level (binary64).

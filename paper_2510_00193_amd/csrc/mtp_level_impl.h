@@ -25,6 +25,13 @@ struct GlobalMoments {
   __device__ __forceinline__ R operator()(int e) const { return p[(long)e * ld]; }
 };
 
+// Per-lane vector held in LDS in [component][lane] layout (conflict-free across a wave).
+template <class R>
+struct LaneVector {
+  const R* p;
+  __device__ __forceinline__ R operator[](int q) const { return p[q * kLaneBlock]; }
+};
+
 template <class R>
 struct RegMoments {
   const R* m;
@@ -167,6 +174,42 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_rev(const R* __restrict_
   L::template rev<G>(M, Cb, mb);
 #pragma unroll
   for (int e = 0; e < NG; ++e) mbar[(long)(LO + e) * ld + li] = mb[e];
+}
+
+// ---------------------------------------------------------------------------- fused program
+// Forward program, energy and basis products, then the reverse program, in one pass over an
+// atom's moments (single-group levels): the contraction adjoints stay in registers instead of
+// taking a round trip through memory, and the moments are read by one kernel instead of two.
+template <class L, class R>
+__global__ __launch_bounds__(kLaneBlock) void k_program(const R* __restrict__ mom, long ld, int i0, int n,
+                                                        const int* __restrict__ species,
+                                                        const double* __restrict__ xi,
+                                                        const double* __restrict__ shift, int nsp,
+                                                        double* __restrict__ e_atom, R* __restrict__ mbar) {
+  static_assert(L::NGROUP == 1, "the fused program needs all moment entries in one group");
+  // contraction adjoints parked in LDS between the two programs (registers are the limit)
+  __shared__ R cbs[L::NCOMP * kLaneBlock];
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int li = b * kLaneBlock + threadIdx.x;
+  if (li >= n) return;
+  GlobalMoments<R> M{mom + li, ld};
+  {
+    R C[L::NCOMP], Cb[L::NCOMP];
+    L::template fwd<R>(M, C);
+    const double e = L::template products<false, R>(C, xi, Cb, nullptr, ld);
+    const int i = i0 + li;
+    e_atom[i] = e + shift[clamp_species(species[i], nsp)];
+#pragma unroll
+    for (int q = 0; q < L::NCOMP; ++q) cbs[q * kLaneBlock + threadIdx.x] = Cb[q];
+  }
+  // the reverse program re-reads the moments it needs: no loaded value stays live across
+  asm volatile("" ::: "memory");
+  R mb[L::NMOM];
+#pragma unroll
+  for (int e = 0; e < L::NMOM; ++e) mb[e] = R(0);
+  L::template rev<0>(M, LaneVector<R>{cbs + threadIdx.x}, mb);
+#pragma unroll
+  for (int e = 0; e < L::NMOM; ++e) mbar[(long)e * ld + li] = mb[e];
 }
 
 // ---------------------------------------------------------------------------- backward pairs
@@ -487,7 +530,17 @@ struct EnergyChain {
     dispatch_backward<L, R, BATCH>(grp, a, i0, n, mb, ld, gout, acc, wpart, watom, s,
                                    std::make_index_sequence<L::NGROUP>{});
   }
-  static ChainOps ops() { return ChainOps{&moments, &prog_fwd, &prog_rev, &backward}; }
+  static void program(const void* m, long ld, int i0, int n, const int* species, const double* xi,
+                      const double* shift, int nsp, double* e_atom, void* mb, hipStream_t s) {
+    if constexpr (L::NGROUP == 1) {
+      const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+      hipLaunchKernelGGL((k_program<L, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, i0, n, species, xi,
+                         shift, nsp, e_atom, (R*)mb);
+    }
+  }
+  static ChainOps ops() {
+    return ChainOps{&moments, &prog_fwd, &prog_rev, &backward, L::NGROUP == 1 && !BATCH ? &program : nullptr};
+  }
 };
 
 template <class L>

@@ -370,6 +370,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
     const long nblocks = ((long)n + kLaneBlockHost - 1) / kLaneBlockHost + (n / chunk + 1);
     if ((rc = m->mbar.reserve((size_t)L.nmom * ld * sizeof(double))) ||
         (rc = m->g.reserve((size_t)std::max<long long>(nl.n_pairs, 1) * 3 * sizeof(double))) ||
+        (rc = m->fown.reserve((size_t)std::max(n, 1) * 3 * sizeof(double))) ||
         (rc = m->wpart.reserve((size_t)nblocks * 6 * sizeof(double))))
       return rc;
   }
@@ -393,7 +394,8 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       }
       {
         ProfScope ps(&m->prof, P_BACKWARD, s);
-        K.backward(0, a, i0, cn, mbar, ld, (double*)m->g.p, 0, (double*)m->wpart.p + 6 * blk, nullptr, s);
+        K.backward(0, a, i0, cn, mbar, ld, (double*)m->g.p, 0, (double*)m->wpart.p + 6 * blk, nullptr,
+                   (double*)m->fown.p, s);
       }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
       continue;
@@ -412,7 +414,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       for (int g = 0; g < L.ngroup; ++g) {
         ProfScope ps(&m->prof, P_BACKWARD, s);
         K.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, nullptr,
-                   s);
+                   (double*)m->fown.p, s);
       }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
     }
@@ -448,7 +450,8 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
   }
   if (forces && n > 0) {
     ProfScope ps(&m->prof, P_GATHER, s);
-    launch_gather_forces(use.off, use.rev, (const double*)m->g.p, n, use.n_pairs, forces, s);
+    launch_gather_forces(use.off, use.rev, (const double*)m->g.p, (const double*)m->fown.p, n, use.n_pairs,
+                         forces, s);
   }
   if (virial) {
     ProfScope ps(&m->prof, P_REDUCE, s);

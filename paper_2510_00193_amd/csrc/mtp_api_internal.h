@@ -56,7 +56,7 @@ struct mtp_model {
   double rmin = 0, rcut = 0, grade_select = 0, grade_break = 0;
   DevBuf radial, linear, shift;                        // coefficients (device)
   DevBuf nl_off, nl_j, nl_shift, nl_rev;               // internally built neighbour list
-  DevBuf mom, cbar, mbar, bvals, g, eatom, wpart;      // per-chunk / per-pair workspace
+  DevBuf mom, cbar, mbar, bvals, g, fown, eatom, wpart;  // per-chunk / per-pair workspace
   DevBuf mdot, cbard, mbard, xout, dxi_part, cpart;   // parameter-adjoint workspace
   DevBuf scratch;
   long wblocks = 0;

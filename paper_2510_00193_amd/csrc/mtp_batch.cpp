@@ -39,7 +39,7 @@ struct mtp_batch {
   DevBuf atom_off, cfg, cells, cinv, reach, off, nj, shift, rev, perm;
   std::vector<int> h_off;          // host copy of the CSR offsets (neighbour counts)
   // workspace
-  DevBuf eatom, watom, g, forces, energy, virial, mom, cbar, mbar, mdot, cbard, mbard, xout, dxi_part,
+  DevBuf eatom, watom, g, fown, forces, energy, virial, mom, cbar, mbar, mdot, cbard, mbard, xout, dxi_part,
       cpart, wpart, ebar_cfg, fbar, parts, zeros;
   // schedule
   int sorted = 0, chunk = 0;
@@ -86,6 +86,7 @@ static int reserve_run(mtp_batch* b) {
   int rc;
   if ((rc = b->eatom.reserve(n * 8)) || (rc = b->watom.reserve(6 * n * 8)) ||
       (rc = b->g.reserve(std::max<long long>(b->npairs, 1) * 24)) || (rc = b->forces.reserve(3 * n * 8)) ||
+      (rc = b->fown.reserve(3 * n * 8)) ||
       (rc = b->energy.reserve(b->ncfg * 8)) || (rc = b->virial.reserve(6 * b->ncfg * 8)) ||
       (rc = b->mom.reserve(L.nmom * ld * 8)) || (rc = b->cbar.reserve(L.ncomp * ld * 8)) ||
       (rc = b->mbar.reserve(L.nmom * ld * 8)) || (rc = b->mdot.reserve(L.nmom * ld * 8)) ||
@@ -169,7 +170,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     }
     for (int gi = 0; gi < L.ngroup; ++gi) {
       ProfScope ps(&m->prof, P_BACKWARD, s);
-      K.backward(gi, a, (int)i0, cn, b->mbar.p, ld, g, gi > 0, wpart + 6 * blk, wa, s);
+      K.backward(gi, a, (int)i0, cn, b->mbar.p, ld, g, gi > 0, wpart + 6 * blk, wa, (double*)b->fown.p, s);
     }
     blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
   }
@@ -177,7 +178,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
   double* E = energy ? energy : (double*)b->energy.p;
   {
     ProfScope ps(&m->prof, P_GATHER, s);
-    launch_gather_forces(a.off, (const int*)b->rev.p, g, n, b->npairs, F, s);
+    launch_gather_forces(a.off, (const int*)b->rev.p, g, (const double*)b->fown.p, n, b->npairs, F, s);
   }
   {
     ProfScope ps(&m->prof, P_REDUCE, s);

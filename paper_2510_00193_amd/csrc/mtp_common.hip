@@ -14,21 +14,26 @@ constexpr int kSumThreads = 1024;
 // F_k = sum over row k of (g[p] - g[rev[p]]): the atom's own pair gradients minus the
 // gradients of the pairs that have k as neighbour (newton's third law through rev).
 // A group of kGatherLanes lanes owns one atom: its row of g is read contiguously, the mirrored
-// entries are gathered, and the group sums with a fixed butterfly (deterministic).
+// entries are gathered, and the group sums with a fixed butterfly (deterministic).  With FOWN
+// the own sums come precomputed per atom (accumulated by the pair kernel) and only the
+// mirrored gradients are read.
 constexpr int kGatherLanes = 16;
 
+template <bool FOWN>
 __global__ __launch_bounds__(kNT) void k_gather(const int* __restrict__ off, const int* __restrict__ rev,
-                                                const double* __restrict__ g, int n, long long npairs,
-                                                double* __restrict__ f) {
+                                                const double* __restrict__ g, const double* __restrict__ fown,
+                                                int n, long long npairs, double* __restrict__ f) {
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int k = b * (kNT / kGatherLanes) + threadIdx.x / kGatherLanes;
   const int lane = threadIdx.x % kGatherLanes;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   if (k < n) {
     for (int p = off[k] + lane; p < off[k + 1]; p += kGatherLanes) {
-      fx += g[3L * p];
-      fy += g[3L * p + 1];
-      fz += g[3L * p + 2];
+      if (!FOWN) {
+        fx += g[3L * p];
+        fy += g[3L * p + 1];
+        fz += g[3L * p + 2];
+      }
       const long q = rev[p];
       if (q >= 0 && q < npairs) {  // a list not made by this library may lack mirrors
         fx -= g[3 * q];
@@ -44,6 +49,11 @@ __global__ __launch_bounds__(kNT) void k_gather(const int* __restrict__ off, con
     fz += __shfl_xor(fz, s, kGatherLanes);
   }
   if (k < n && lane == 0) {
+    if (FOWN) {
+      fx = fown[3L * k] + fx;
+      fy = fown[3L * k + 1] + fy;
+      fz = fown[3L * k + 2] + fz;
+    }
     f[3L * k] = fx;
     f[3L * k + 1] = fy;
     f[3L * k + 2] = fz;
@@ -189,11 +199,16 @@ void launch_species_grad(const int* species, int n, int nsp, double ebar, double
   hipLaunchKernelGGL(k_species_grad, dim3(1), dim3(kNT), 0, s, species, n, nsp, ebar, out);
 }
 
-void launch_gather_forces(const int* off, const int* rev, const double* g, int n, long long npairs,
-                          double* forces, hipStream_t s) {
+void launch_gather_forces(const int* off, const int* rev, const double* g, const double* fown, int n,
+                          long long npairs, double* forces, hipStream_t s) {
   if (n <= 0) return;
   const int per = kNT / kGatherLanes;
-  hipLaunchKernelGGL(k_gather, dim3((n + per - 1) / per), dim3(kNT), 0, s, off, rev, g, n, npairs, forces);
+  if (fown)
+    hipLaunchKernelGGL(k_gather<true>, dim3((n + per - 1) / per), dim3(kNT), 0, s, off, rev, g, fown, n, npairs,
+                       forces);
+  else
+    hipLaunchKernelGGL(k_gather<false>, dim3((n + per - 1) / per), dim3(kNT), 0, s, off, rev, g, fown, n, npairs,
+                       forces);
 }
 
 // out[c] = sum_i x[i * stride + c] for c < ncomp; part holds ncomp * kPartBlocks doubles.

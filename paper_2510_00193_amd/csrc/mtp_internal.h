@@ -35,8 +35,9 @@ struct ChainOps {
                    const double* xi, const double* shift, int nsp, double* e_atom, void* cbar,
                    double* bout, hipStream_t s);
   void (*prog_rev)(int g, const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s);
+  // fown (optional, [atom][3]): (+)= the atom's own pair-gradient sum, for launch_gather_forces
   void (*backward)(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
-                   int acc, double* wpart, double* watom, hipStream_t s);
+                   int acc, double* wpart, double* watom, double* fown, hipStream_t s);
   // forward + products + reverse in one kernel (single-group levels, one system; else null):
   // writes e_atom[i0 + k] and the moment adjoints
   void (*program)(const void* m, long ld, int i0, int n, const int* species, const double* xi,
@@ -94,8 +95,9 @@ NbrWork* nbr_work_create();
 void nbr_work_destroy(NbrWork* w);
 
 // level-independent kernels (mtp_common.hip)
-void launch_gather_forces(const int* off, const int* rev, const double* g, int n, long long npairs,
-                          double* forces, hipStream_t s);
+// forces = (fown ? fown : own row sums of g) - mirrored gradients g[rev[p]]
+void launch_gather_forces(const int* off, const int* rev, const double* g, const double* fown, int n,
+                          long long npairs, double* forces, hipStream_t s);
 void launch_sum(const double* x, long n, long stride, double* out, hipStream_t s);
 // Two-level deterministic sums of ncomp strided components (part: ncomp * kSumParts doubles).
 constexpr int kSumParts = 256;

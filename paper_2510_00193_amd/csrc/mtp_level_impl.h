@@ -213,13 +213,15 @@ __global__ __launch_bounds__(kLaneBlock) void k_program(const R* __restrict__ mo
 }
 
 // ---------------------------------------------------------------------------- backward pairs
-// g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials.
+// g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials;
+// fown[i] (+)= sum of the atom's own g over its row (the first half of its force), when given.
 template <class L, int G, class R, bool BATCH, int NC>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
                                                          const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
                                                          double* __restrict__ wpart,
-                                                         double* __restrict__ watom) {
+                                                         double* __restrict__ watom,
+                                                         double* __restrict__ fown) {
   __shared__ R csh[kMaxRadial];
   __shared__ double red[kLaneBlock];
   stage_radial(a, csh);
@@ -227,6 +229,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
   const int li = b * kLaneBlock + threadIdx.x;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   double w[6] = {0, 0, 0, 0, 0, 0};
+  double fo[3] = {0, 0, 0};  // sum of the atom's own pair gradients
   if (li < n) {
     const int i = sweep_atom<BATCH>(a, i0 + li);
     double H[9];
@@ -255,6 +258,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
         g[3L * p + 1] = gy;
         g[3L * p + 2] = gz;
       }
+      fo[0] += gx;
+      fo[1] += gy;
+      fo[2] += gz;
       w[0] -= dx * gx;
       w[1] -= dy * gy;
       w[2] -= dz * gz;
@@ -265,6 +271,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     if constexpr (BATCH) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) watom[6L * i + k] = accumulate ? watom[6L * i + k] + w[k] : w[k];
+    }
+    if (fown) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) fown[3L * i + k] = accumulate ? fown[3L * i + k] + fo[k] : fo[k];
     }
   }
 #pragma unroll
@@ -478,17 +488,17 @@ void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipSt
 }
 template <class L, int G, class R, bool BATCH>
 void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
-                       int acc, double* wpart, double* watom, hipStream_t s) {
+                       int acc, double* wpart, double* watom, double* fown, hipStream_t s) {
   const int nb = (n + kLaneBlock - 1) / kLaneBlock;
   if (a.ncheb == 8)
     hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
-                       (const R*)mb, ld, g, acc, wpart, watom);
+                       (const R*)mb, ld, g, acc, wpart, watom, fown);
   else if (a.ncheb == 10)
     hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
-                       (const R*)mb, ld, g, acc, wpart, watom);
+                       (const R*)mb, ld, g, acc, wpart, watom, fown);
   else
     hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
-                       (const R*)mb, ld, g, acc, wpart, watom);
+                       (const R*)mb, ld, g, acc, wpart, watom, fown);
 }
 
 template <class L, class R, bool BATCH, size_t... Gs>
@@ -503,9 +513,9 @@ void dispatch_rev(int g, const void* m, long ld, int n, const void* cb, void* mb
 }
 template <class L, class R, bool BATCH, size_t... Gs>
 void dispatch_backward(int g, const SysArgs& a, int i0, int n, const void* mb, long ld,
-                       double* gout, int acc, double* wpart, double* watom, hipStream_t s,
+                       double* gout, int acc, double* wpart, double* watom, double* fown, hipStream_t s,
                        std::index_sequence<Gs...>) {
-  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R, BATCH>(a, i0, n, mb, ld, gout, acc, wpart, watom, s)
+  ((g == (int)Gs ? launch_backward_g<L, (int)Gs, R, BATCH>(a, i0, n, mb, ld, gout, acc, wpart, watom, fown, s)
                  : void()),
    ...);
 }
@@ -526,8 +536,8 @@ struct EnergyChain {
     dispatch_rev<L, R>(g, m, ld, n, cb, mb, s, std::make_index_sequence<L::NGROUP>{});
   }
   static void backward(int grp, const SysArgs& a, int i0, int n, const void* mb, long ld, double* gout,
-                       int acc, double* wpart, double* watom, hipStream_t s) {
-    dispatch_backward<L, R, BATCH>(grp, a, i0, n, mb, ld, gout, acc, wpart, watom, s,
+                       int acc, double* wpart, double* watom, double* fown, hipStream_t s) {
+    dispatch_backward<L, R, BATCH>(grp, a, i0, n, mb, ld, gout, acc, wpart, watom, fown, s,
                                    std::make_index_sequence<L::NGROUP>{});
   }
   static void program(const void* m, long ld, int i0, int n, const int* species, const double* xi,

@@ -385,12 +385,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(PlanArgs pa, const int
                                                           const int* __restrict__ binimg, int cap,
                                                           long long* __restrict__ rows,
                                                           int* __restrict__ counts, int* __restrict__ flag) {
-  constexpr int kSurv = 2 * ROWCAP;  // filter survivors kept per centre
+  static_assert(MAXC % 64 == 0, "staged capacity in whole waves");
   __shared__ double px[MAXC], py[MAXC], pz[MAXC];
   __shared__ long long ckey[MAXC];
   __shared__ int cslot[MAXC];
-  __shared__ long long hits[kBinWaves][ROWCAP];
-  __shared__ unsigned short surv[kBinWaves][kSurv];
+  static_assert(ROWCAP % 4 == 0, "padded hit lists");
+  __shared__ __align__(16) long long hits[kBinWaves][ROWCAP];
+  __shared__ unsigned short surv[kBinWaves][MAXC];
   __shared__ int bst[27], boff[28], bwrap[27];
   __shared__ int skip;
   const int bid = blockIdx.x;
@@ -432,7 +433,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(PlanArgs pa, const int
     if (threadIdx.x == 0) flag[3] = 1;
     return;
   }
-  for (int k = threadIdx.x; k < ncand; k += kBinThreads) {
+  const int npad = (ncand + 63) & ~63;  // staged list padded to whole waves with far points
+  for (int k = threadIdx.x; k < npad; k += kBinThreads) {
+    if (k >= ncand) {
+      px[k] = py[k] = pz[k] = 1e300;
+      continue;
+    }
     int lo = 0, hi = 26;  // bin t with boff[t] <= k < boff[t + 1]
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -468,29 +474,19 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(PlanArgs pa, const int
     double ox, oy, oz;
     shift_vec(oi0, oi1, oi2, pa.H, ox, oy, oz);
     const double qx = rix - ox, qy = riy - oy, qz = riz - oz;
-    // 1. filter
+    // 1. filter (padding fails it; survivors compacted in candidate order)
     int ns = 0;
-    for (int q0 = 0; q0 < ncand; q0 += 64) {
+    for (int q0 = 0; q0 < npad; q0 += 64) {
       const int q = q0 + lane;
-      bool pass = false;
-      if (q < ncand) {
-        const double ex = px[q] - qx, ey = py[q] - qy, ez = pz[q] - qz;
-        pass = fma(ez, ez, fma(ey, ey, ex * ex)) < rc2f;
-      }
+      const double ex = px[q] - qx, ey = py[q] - qy, ez = pz[q] - qz;
+      const bool pass = fma(ez, ez, fma(ey, ey, ex * ex)) < rc2f;
       const unsigned long long mask = __ballot(pass);
-      if (pass) {
-        const int slot = ns + __popcll(mask & below);
-        if (slot < kSurv) sw[slot] = (unsigned short)q;
-      }
+      if (pass) sw[ns + __popcll(mask & below)] = (unsigned short)q;
       ns += __popcll(mask);
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    if (ns > kSurv) {
-      if (lane == 0) flag[3] = 1;
-      continue;
-    }
-    // 2. exact test of the survivors
+    // 2. exact test of the survivors; hits compacted into the wave's LDS list
     const long long self = make_key(i, 0, 0, 0);
     const long long koff = ((long long)oi0 << 16) + ((long long)oi1 << 8) + (long long)oi2;
     int cnt = 0;
@@ -518,21 +514,29 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(PlanArgs pa, const int
       }
       cnt += __popcll(mask);
     }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
     if (cnt > cap || cnt > ROWCAP) {
       if (lane == 0) flag[3] = 1;
       continue;
     }
+    // 3. rank of each hit among the hits (keys are distinct) -> sorted row; the list is padded
+    // to a multiple of 4 with keys above every real key, read four at a time (broadcast)
+    const int cnt4 = (cnt + 3) & ~3;
+    if (lane < cnt4 - cnt) hw[cnt + lane] = LLONG_MAX;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
     for (int h = lane; h < cnt; h += 64) {
       const long long k = hw[h];
       int rank = 0;
-      for (int t = 0; t < cnt; ++t) rank += hw[t] < k;
+      for (int t = 0; t < cnt4; t += 4) {
+        const longlong2 u = *reinterpret_cast<const longlong2*>(hw + t);
+        const longlong2 v = *reinterpret_cast<const longlong2*>(hw + t + 2);
+        rank += (int)(u.x < k) + (int)(u.y < k) + (int)(v.x < k) + (int)(v.y < k);
+      }
       rows[(long)i * cap + rank] = k;
     }
-    if (lane == 0) counts[i] = cnt;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
+    if (lane == 0) counts[i] = cnt;
   }
 }
 
@@ -556,9 +560,8 @@ __global__ __launch_bounds__(256) void k_rows_to_csr(int n, int cap, const long 
               n3 = (int)(key & 0xFF) - 128;
     nj[o + k] = j;
     shift[o + k] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
-    const long long sk = key & 0xFFFFFF;
     const long long want = make_key(i, -n1, -n2, -n3);
-    const bool owner = j > i || (j == i && sk > (want & 0xFFFFFF));
+    const bool owner = j > i || (j == i && (key & 0xFFFFFF) > (want & 0xFFFFFF));
     if (rev && owner) {
       const long long* rj = rows + (long)j * cap;
       int lo = 0, hi = counts[j] - 1, found = -1;
@@ -882,7 +885,7 @@ int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, dou
     const long long* rows = w->get<long long>(S_ROWS, 1);
     int* counts = w->get<int>(S_COUNTS, n);
     if (n > 0)
-      hipLaunchKernelGGL(k_rows_to_csr, dim3((n + 3) / 4), dim3(256), 0, s, n, w->row_cap, rows, counts, off, nj,
+      hipLaunchKernelGGL(k_rows_to_csr, dim3((n + 7) / 8), dim3(256), 0, s, n, w->row_cap, rows, counts, off, nj,
                          shift, rev);
     if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
     return 0;

@@ -71,7 +71,8 @@ typedef struct {
   const double* shift;   /* host [n_species], per-species energy constant s */
   int precision;         /* MTP_FP64 or MTP_FP32_MOMENTS */
   int chunk_atoms;       /* atoms evaluated per chunk (bounds workspace, cf. the paper's
-                            chunksize, Section 2.3); 0 = library default */
+                            chunksize, Section 2.3); 0 = library default (1,048,576 atoms,
+                            about 2 KB of workspace per atom at level 16) */
   double grade_select;   /* grade_max above this returns MTP_GRADE_SELECT; <= 0 disables */
   double grade_break;    /* grade_max above this returns MTP_GRADE_BREAK; <= 0 disables */
 } mtp_params;

@@ -215,7 +215,16 @@ def _emit_inner(w, lst, var):
             w(f"  {var} = fma({_lit(wgt)}, {_ref(y)}, {var});")
 
 
+# Moment loads kept in flight by the reverse program (whose blocks are fenced to bound register
+# pressure): each contraction block takes its entries from a ring of prefetched values and
+# issues the load that many positions ahead, so the global-memory latency of one block is
+# covered by the arithmetic of the blocks before it.
+PREFETCH_DEPTH = int(os.environ.get("MTP_PREFETCH_DEPTH", "24"))
+
+
 def _emit_components_forward(w: _W, prog: Program):
+    """Connected contractions.  No block fences here: the blocks are independent and the
+    scheduler interleaves them freely (their loads overlap the arithmetic of other blocks)."""
     w("template <class R, class MA>")
     w("static __device__ __forceinline__ void fwd(const MA& M, R* __restrict__ C) {")
     w.push()
@@ -238,14 +247,22 @@ def _emit_components_reverse(w: _W, prog: Program, groups):
         w("template <class R, class MA, class CB>")
         w(f"static __device__ __forceinline__ void rev_g{gi}(const MA& M, const CB& Cb, R* __restrict__ mb) {{")
         w.push()
-        for blk in prog.blocks:
-            if not any(lo <= e < hi for e in blk.entries):
-                continue
+        blocks = [blk for blk in prog.blocks if any(lo <= e < hi for e in blk.entries)]
+        seq = [e for blk in blocks for e in blk.entries]   # every moment load, in program order
+        depth = max(1, min(PREFETCH_DEPTH, len(seq)))
+        for k in range(depth):
+            w(f"R pf{k} = M({seq[k]});")
+        pos = 0
+        for blk in blocks:
             w(f"{{  // contraction {blk.q}")
             w.push()
             w("MTP_BLOCK_FENCE();")
             for e in blk.entries:
-                w(f"const R me{e} = M({e});")
+                slot = pos % depth
+                w(f"const R me{e} = pf{slot};")
+                if pos + depth < len(seq):
+                    w(f"pf{slot} = M({seq[pos + depth]});")
+                pos += 1
             w(f"const R cb = Cb[{blk.q}];")
             _emit_block_forward(w, blk, with_output=False)
             for k in range(blk.n_temp):

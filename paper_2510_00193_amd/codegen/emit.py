@@ -110,14 +110,28 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
                 lows.add((a, b - 1, c))
             if c:
                 lows.add((a, b, c - 1))
-        need = _monomial_closure(set(by_mono.keys()) | lows)
         mus = sorted({items[e][0] for e in ents})
         for mu in mus:
             w(f"R s{mu} = R(0);")
+        made = set()
+
+        def make(abc):
+            # a monomial is formed right before its first use (its chain parent first), so
+            # that few monomials of the current degree are live at once
+            if abc in made:
+                return
+            a, b, c = abc
+            if a + b + c:
+                make((a, b, c - 1) if c else (a, b - 1, 0) if b else (a - 1, 0, 0))
+            _emit_one_monomial(w, abc)
+            made.add(abc)
+
         for nu in range(gnu + 1):
-            for abc in _degree(need, nu):
-                _emit_one_monomial(w, abc)
             for abc in _degree(by_mono.keys(), nu):
+                make(abc)
+                for low in ((abc[0] - 1, abc[1], abc[2]), (abc[0], abc[1] - 1, abc[2]), (abc[0], abc[1], abc[2] - 1)):
+                    if min(low) >= 0:
+                        make(low)
                 lst = by_mono[abc]
                 for e, mu in lst:
                     w(f"s{mu} = fma(mb[{e - lo}], {_mono_name(abc)}, s{mu});")

@@ -17,6 +17,7 @@ emitted too, for argument checking and tests.
 """
 from __future__ import annotations
 
+import math
 import os
 from collections import defaultdict
 from fractions import Fraction
@@ -88,6 +89,8 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
         w("template <class R>")
         w(f"static __device__ __forceinline__ void acc_moments_g{gi}(R* __restrict__ m, const R* __restrict__ f, R x, R y, R z) {{")
         w.push()
+        # degree by degree: the monomials of one degree are independent products, formed
+        # together (measured faster here than forming each right before its accumulations)
         need = _monomial_closure(by_mono.keys())
         for nu in range(gnu + 1):
             for abc in _degree(need, nu):
@@ -98,32 +101,36 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
         w.pop()
         w("}")
         # ---------------- gradient of sum_e mb_e f_mu_e mono_e, and u = sum_mu fp_mu S_mu
+        # In scaled monomials q_abc = x^a y^b z^c / (a! b! c!) the gradient of q_abc is
+        # (q_(a-1)bc, q_a(b-1)c, q_ab(c-1)) without factors, so the caller passes the adjoints
+        # multiplied by a! b! c! (MFACT): mb_e mono_e = (mb_e a!b!c!) q_e.
         w("template <class R>")
         w(f"static __device__ __forceinline__ void pair_grad_g{gi}(const R* __restrict__ mb, const R* __restrict__ f,")
         w("    const R* __restrict__ fp, R x, R y, R z, R& gx, R& gy, R& gz, R& u) {")
         w.push()
-        lows = set()
-        for (a, b, c) in by_mono:
-            if a:
-                lows.add((a - 1, b, c))
-            if b:
-                lows.add((a, b - 1, c))
-            if c:
-                lows.add((a, b, c - 1))
         mus = sorted({items[e][0] for e in ents})
         for mu in mus:
             w(f"R s{mu} = R(0);")
+        top = max(max(k) for k in by_mono)
+        for var in "xyz":
+            for k in range(2, top + 1):
+                w(f"const R {var}_{k} = {var} * {_lit(Fraction(1, k))};")
         made = set()
 
         def make(abc):
-            # a monomial is formed right before its first use (its chain parent first), so
-            # that few monomials of the current degree are live at once
+            # a scaled monomial is formed right before its first use (its chain parent first),
+            # so that few monomials of the current degree are live at once
             if abc in made:
                 return
             a, b, c = abc
-            if a + b + c:
-                make((a, b, c - 1) if c else (a, b - 1, 0) if b else (a - 1, 0, 0))
-            _emit_one_monomial(w, abc)
+            name = _mono_name(abc)
+            if a + b + c == 0:
+                w(f"const R {name} = R(1);")
+            else:
+                parent, var, k = ((a, b, c - 1), "z", c) if c else ((a, b - 1, 0), "y", b) if b else ((a - 1, 0, 0), "x", a)
+                make(parent)
+                fac = var if k == 1 else f"{var}_{k}"
+                w(f"const R {name} = {_mono_name(parent)} * {fac};")
             made.add(abc)
 
         for nu in range(gnu + 1):
@@ -146,12 +153,8 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
                     else:
                         w(f"  t = fma(f[{mu}], mb[{e - lo}], t);")
                 for var, k, low in (("gx", a, (a - 1, b, c)), ("gy", b, (a, b - 1, c)), ("gz", c, (a, b, c - 1))):
-                    if k == 0:
-                        continue
-                    if k == 1:
+                    if k:
                         w(f"  {var} = fma(t, {_mono_name(low)}, {var});")
-                    else:
-                        w(f"  {var} = fma(R({k}) * t, {_mono_name(low)}, {var});")
                 w("}")
         for mu in mus:
             w(f"u = fma(fp[{mu}], s{mu}, u);")
@@ -424,6 +427,9 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     w("static constexpr int GROUP_HI[NGROUP] = {" + ", ".join(str(g[1]) for g in groups) + "};")
     w("// flat moment layout: (mu, a, b, c) of component e")
     w("static constexpr int ENTRIES[NMOM][4] = {" + ", ".join("{%d, %d, %d, %d}" % it for it in prog.layout.items) + "};")
+    # a! b! c! of each entry: pair_grad takes the moment adjoints scaled by it
+    w("static constexpr double MFACT[NMOM] = {" + ", ".join(
+        "%d." % (math.factorial(a) * math.factorial(b) * math.factorial(c)) for (_, a, b, c) in prog.layout.items) + "};")
     _emit_pair_functions(w, prog, groups)
     _emit_components_forward(w, prog)
     _emit_components_reverse(w, prog, groups)

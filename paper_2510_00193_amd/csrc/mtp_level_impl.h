@@ -235,8 +235,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     double H[9];
     cell_of<BATCH>(a, i, H);
     R mb[NG];
+    // adjoints scaled by a! b! c! for the scaled monomials of pair_grad
 #pragma unroll
-    for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li];
+    for (int e = 0; e < NG; ++e) mb[e] = mbar[(long)(LO + e) * ld + li] * R(L::MFACT[LO + e]);
     const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
     const int zi = clamp_species(a.species[i], a.nsp);
     const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;

@@ -202,14 +202,17 @@ int main() {
     double r = std::sqrt(x * x + y * y + z * z), f[L::NMU], fp[L::NMU];
     radial(r, f, fp);
     double gx = 0, gy = 0, gz = 0, u = 0;
+    // pair_grad takes the adjoints multiplied by a! b! c! of each entry
+    std::vector<double> mbs(L::NMOM);
+    for (int k = 0; k < L::NMOM; ++k) mbs[k] = mb[k] * L::MFACT[k];
     for (int g = 0; g < L::NGROUP; ++g) {
       const int lo = L::GROUP_LO[g];
-      if (g == 0) L::pair_grad<0>(mb.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
+      if (g == 0) L::pair_grad<0>(mbs.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
 #if MTP_NGROUP > 1
-      if (g == 1) L::pair_grad<1>(mb.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
+      if (g == 1) L::pair_grad<1>(mbs.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
 #endif
 #if MTP_NGROUP > 2
-      if (g == 2) L::pair_grad<2>(mb.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
+      if (g == 2) L::pair_grad<2>(mbs.data() + lo, f, fp, x, y, z, gx, gy, gz, u);
 #endif
     }
     std::vector<double> got = {gx + u * x / r, gy + u * y / r, gz + u * z / r}, want(3);

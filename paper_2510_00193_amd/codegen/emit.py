@@ -111,6 +111,10 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
         mus = sorted({items[e][0] for e in ents})
         for mu in mus:
             w(f"R s{mu} = R(0);")
+        # gradient sums of the monomials with a single radial function, per radial function
+        single = set()
+        for mu in mus:
+            w(f"R hx{mu} = R(0), hy{mu} = R(0), hz{mu} = R(0);")
         top = max(max(k) for k in by_mono)
         for var in "xyz":
             for k in range(2, top + 1):
@@ -145,6 +149,15 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
                 a, b, c = abc
                 if a + b + c == 0:
                     continue
+                dirs = [(d, low) for d, k, low in (("x", a, (a - 1, b, c)), ("y", b, (a, b - 1, c)),
+                                                   ("z", c, (a, b, c - 1))) if k]
+                if len(lst) == 1:
+                    # one radial function: accumulate mb_e grad q_e, multiply by f_mu once per pair
+                    e, mu = lst[0]
+                    single.add(mu)
+                    for d, low in dirs:
+                        w(f"h{d}{mu} = fma(mb[{e - lo}], {_mono_name(low)}, h{d}{mu});")
+                    continue
                 first = True
                 for e, mu in lst:
                     if first:
@@ -152,10 +165,12 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
                         first = False
                     else:
                         w(f"  t = fma(f[{mu}], mb[{e - lo}], t);")
-                for var, k, low in (("gx", a, (a - 1, b, c)), ("gy", b, (a, b - 1, c)), ("gz", c, (a, b, c - 1))):
-                    if k:
-                        w(f"  {var} = fma(t, {_mono_name(low)}, {var});")
+                for d, low in dirs:
+                    w(f"  g{d} = fma(t, {_mono_name(low)}, g{d});")
                 w("}")
+        for mu in sorted(single):
+            for d in "xyz":
+                w(f"g{d} = fma(f[{mu}], h{d}{mu}, g{d});")
         for mu in mus:
             w(f"u = fma(fp[{mu}], s{mu}, u);")
         w.pop()

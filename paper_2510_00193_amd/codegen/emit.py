@@ -112,9 +112,11 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
         for mu in mus:
             w(f"R s{mu} = R(0);")
         # gradient sums of the monomials with a single radial function, per radial function
+        # and degree
         single = set()
         for mu in mus:
-            w(f"R hx{mu} = R(0), hy{mu} = R(0), hz{mu} = R(0);")
+            for n in range(1, gnu + 1):
+                w(f"R hx{mu}_{n} = R(0), hy{mu}_{n} = R(0), hz{mu}_{n} = R(0);")
         top = max(max(k) for k in by_mono)
         for var in "xyz":
             for k in range(2, top + 1):
@@ -144,20 +146,23 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
                     if min(low) >= 0:
                         make(low)
                 lst = by_mono[abc]
+                a, b, c = abc
+                if len(lst) == 1 and a + b + c > 0:
+                    # one radial function: accumulate mb_e grad q_e per degree nu, without the
+                    # radial factor (applied once per pair); the value sum of these terms follows
+                    # from Euler's relation d . grad P = nu P for a homogeneous P of degree nu
+                    e, mu = lst[0]
+                    single.add((mu, nu))
+                    for d, k, low in (("x", a, (a - 1, b, c)), ("y", b, (a, b - 1, c)), ("z", c, (a, b, c - 1))):
+                        if k:
+                            w(f"h{d}{mu}_{nu} = fma(mb[{e - lo}], {_mono_name(low)}, h{d}{mu}_{nu});")
+                    continue
                 for e, mu in lst:
                     w(f"s{mu} = fma(mb[{e - lo}], {_mono_name(abc)}, s{mu});")
-                a, b, c = abc
                 if a + b + c == 0:
                     continue
                 dirs = [(d, low) for d, k, low in (("x", a, (a - 1, b, c)), ("y", b, (a, b - 1, c)),
                                                    ("z", c, (a, b, c - 1))) if k]
-                if len(lst) == 1:
-                    # one radial function: accumulate mb_e grad q_e, multiply by f_mu once per pair
-                    e, mu = lst[0]
-                    single.add(mu)
-                    for d, low in dirs:
-                        w(f"h{d}{mu} = fma(mb[{e - lo}], {_mono_name(low)}, h{d}{mu});")
-                    continue
                 first = True
                 for e, mu in lst:
                     if first:
@@ -168,9 +173,13 @@ def _emit_pair_functions(w: _W, prog: Program, groups):
                 for d, low in dirs:
                     w(f"  g{d} = fma(t, {_mono_name(low)}, g{d});")
                 w("}")
-        for mu in sorted(single):
+        for mu in sorted({m for m, _ in single}):
+            nus = sorted(n for m, n in single if m == mu)
             for d in "xyz":
-                w(f"g{d} = fma(f[{mu}], h{d}{mu}, g{d});")
+                terms = " + ".join(f"h{d}{mu}_{n}" for n in nus)
+                w(f"g{d} = fma(f[{mu}], {terms}, g{d});")
+            for n in nus:
+                w(f"s{mu} = fma(fma(z, hz{mu}_{n}, fma(y, hy{mu}_{n}, x * hx{mu}_{n})), {_lit(Fraction(1, n))}, s{mu});")
         for mu in mus:
             w(f"u = fma(fp[{mu}], s{mu}, u);")
         w.pop()

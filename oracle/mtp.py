@@ -17,7 +17,8 @@ notes of the repository and repeated briefly here:
   B_alpha  = full contraction of the moments of basis function alpha
   E_i      = s[z_i] + sum_alpha xi_alpha B_alpha(i);   E = sum_i E_i
   F_k      = -dE/dR_k;   W = -sum_pairs d_ij (x) dE_i/dd_ij  (xx, yy, zz, xy, xz, yz)
-  grade_i  = max_k |(B_i A^-1)_k|
+  grade_i  = max_k |(B_i A^-1)_k|                  neighbourhood mode
+  grade    = max_k |((sum_i B_i) A^-1)_k|          configuration mode (b = dE/dxi)
 
 Everything is evaluated the plain way: dense 3^nu tensors, one einsum per
 basis function, derivatives by PyTorch autograd (a library primitive), no
@@ -194,6 +195,17 @@ def grade(b, ainv):
     """Neighbourhood-mode grade per atom: max_k |sum_alpha B[i, alpha] Ainv[alpha, k]|."""
     b = np.asarray(b, dtype=np.float64)
     return np.abs(b @ np.asarray(ainv, dtype=np.float64)).max(axis=1)
+
+
+def config_descriptor(b):
+    """Configuration-mode descriptor: sum over atoms of B_i (equal to dE/dxi)."""
+    return np.asarray(b, dtype=np.float64).sum(axis=0)
+
+
+def config_grade(b, ainv):
+    """Configuration-mode grade (Section 2.1 names the mode; the MLIP-3 definition it follows):
+    max_k |(sum_i B_i) A^-1|_k for one configuration."""
+    return float(np.abs(config_descriptor(b) @ np.asarray(ainv, dtype=np.float64)).max())
 
 
 def param_vjp(model, struct, ebar, fbar, nl=None):

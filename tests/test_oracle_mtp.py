@@ -224,6 +224,29 @@ def test_grade_identity_and_maxvol():
     np.testing.assert_allclose(g[chosen], 1.0, rtol=1e-9)
 
 
+def test_config_grade_descriptor_is_energy_gradient_and_maxvol():
+    """Configuration mode: the descriptor equals dE/dxi (autograd through the whole energy), and
+    configurations whose descriptors form A have grade 1 (MaxVol property)."""
+    rng = np.random.default_rng(57)
+    model = _model(6, 2, rng)
+    n_alpha = len(model.basis)
+    structs = wl.random_cell_batch(rng, n_alpha + 2, 8, 20, 0.06, 1.8, 2)
+    desc = []
+    for k, st in enumerate(structs):
+        b = om.energy_forces_virial(model, st)["B"].detach().numpy()
+        if k < 2:
+            dxi, _, _ = om.param_vjp(model, st, 1.0, np.zeros((st.n_atoms, 3)))
+            assert _rel(om.config_descriptor(b), dxi) < 1e-12
+        desc.append(om.config_descriptor(b))
+    desc = np.array(desc)
+    a = desc[:n_alpha]
+    ainv = np.linalg.inv(a)
+    for k, st in enumerate(structs[:n_alpha]):
+        b = om.energy_forces_virial(model, st)["B"].detach().numpy()
+        assert abs(om.config_grade(b, ainv) - 1.0) < 1e-8
+    assert om.config_grade(np.eye(n_alpha)[:1], np.eye(n_alpha)) == 1.0
+
+
 # ----------------------------------------------------------------------------- parameter gradients
 
 

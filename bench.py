@@ -142,7 +142,8 @@ def section_fp32(s, params, pos, sp, ref, steps):
 
 
 def section_grade(steps):
-    """Neighbourhood grade on the 250,000-atom fcc workload (prebuilt list), FP64 and FP32-split."""
+    """Neighbourhood grade on the 250,000-atom fcc workload (prebuilt list), FP64 and FP32-split,
+    and the configuration-mode grade of the same configuration."""
     import torch
     from paper_2510_00193_amd import Potential, level_info
     info = level_info(16)
@@ -173,6 +174,10 @@ def section_grade(steps):
     g32 = pot.grade(pos, sp, s.cell, ainv, nlist=nl, mode="fp32split")["grade"]
     torch.cuda.synchronize()
     out["fp32split"]["rel_err_vs_fp64"] = float(((g32 - g64).abs() / g64.clamp(min=1.0)).max().cpu())
+    # configuration mode on the same configuration: descriptor sum_i B_i, then one product
+    pot.grade_config(pos, sp, s.cell, ainv, nlist=nl)
+    dt = _timeit(lambda: pot.grade_config(pos, sp, s.cell, ainv, nlist=nl), steps, warmup=0)
+    out["config_mode"] = {"value": s.n_atoms / dt, "unit": "atom-steps/s", "ms_per_step": dt * 1e3}
     out["workload"] = f"fcc-50x50x25-3sp-L16: {s.n_atoms} atoms, n_alpha {info['n_alpha']}"
     return out
 

@@ -146,6 +146,14 @@ int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double
 int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
               int mode, double* grade, double* grade_max, void* stream);
 
+/* Configuration-mode extrapolation grade (the second active-learning mode of Section 2.1; the
+ * definition is MLIP-3's): descriptor b [n_alpha] = sum_i B_i (= dE/dxi), reduced over atoms in
+ * a fixed order, and grade [1] (device) = max_k |(b Ainv)_k|.  ainv: device [n_alpha][n_alpha]
+ * row-major.  descriptor: device [n_alpha] output, or NULL.  Thresholds as for mtp_grade, with
+ * the configuration's grade in place of grade_max. */
+int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
+                     double* descriptor, double* grade, void* stream);
+
 /* Vector-Jacobian product of (E, F) with respect to the coefficients:
  *   d_linear [n_alpha], d_radial [n_species^2 n_mu n_cheb], d_shift [n_species] (device) =
  *   ebar dE/dtheta + sum_k fbar_k . dF_k/dtheta,  fbar device [N][3].

@@ -25,7 +25,7 @@ MTP_GRADE_FP32SPLIT = 1
 
 EXPORTS = ("mtp_batch_create", "mtp_batch_run", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
            "mtp_batch_neighbors", "mtp_batch_destroy", "mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset", "mtp_create", "mtp_destroy", "mtp_last_error", "mtp_sizes", "mtp_set_params",
-           "mtp_neighbors", "mtp_compute", "mtp_grade", "mtp_param_grad")
+           "mtp_neighbors", "mtp_compute", "mtp_grade", "mtp_grade_config", "mtp_param_grad")
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -104,6 +104,8 @@ def open_library(path: str):
     lib.mtp_compute.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), vp, vp, vp, vp, vp]
     if hasattr(lib, "mtp_grade"):
         lib.mtp_grade.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), vp, i, vp, vp, vp]
+    if hasattr(lib, "mtp_grade_config"):
+        lib.mtp_grade_config.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), vp, vp, vp, vp]
     if hasattr(lib, "mtp_param_grad"):
         lib.mtp_param_grad.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), d, vp, vp, vp,
                                        vp, vp]
@@ -121,7 +123,7 @@ def open_library(path: str):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset",
                  "mtp_create", "mtp_sizes", "mtp_set_params", "mtp_neighbors", "mtp_compute",
-                 "mtp_grade", "mtp_param_grad"):
+                 "mtp_grade", "mtp_grade_config", "mtp_param_grad"):
         if hasattr(lib, name):
             getattr(lib, name).restype = ctypes.c_int
     return lib

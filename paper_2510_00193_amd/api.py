@@ -202,6 +202,20 @@ class Potential:
                      (_lib.MTP_OK, _lib.MTP_GRADE_SELECT, _lib.MTP_GRADE_BREAK))
         return {"grade": g, "grade_max": gm[0], "status": code}
 
+    def grade_config(self, pos, species, cell, ainv, nlist=None):
+        """Configuration-mode grade: {'grade': max_k |(sum_i B_i) Ainv|_k (device scalar),
+        'descriptor': sum_i B_i [n_alpha], 'status'}."""
+        sysc, n = self._system(pos, species, cell)
+        dev = pos.device
+        _dev(ainv, torch.float64, (self.n_alpha, self.n_alpha), "ainv")
+        g = torch.empty(1, dtype=torch.float64, device=dev)
+        desc = torch.empty(self.n_alpha, dtype=torch.float64, device=dev)
+        nl = ctypes.byref(nlist._c()) if nlist is not None else None
+        code = check(self._lib.mtp_grade_config(self._h, ctypes.byref(sysc), nl, _ptr(ainv), _ptr(desc), _ptr(g),
+                                                _stream()),
+                     (_lib.MTP_OK, _lib.MTP_GRADE_SELECT, _lib.MTP_GRADE_BREAK))
+        return {"grade": g[0], "descriptor": desc, "status": code}
+
     def param_grad(self, pos, species, cell, ebar, fbar, nlist=None):
         sysc, n = self._system(pos, species, cell)
         dev = pos.device

@@ -503,6 +503,54 @@ extern "C" int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* n
   return MTP_OK;
 }
 
+extern "C" int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
+                                double* descriptor, double* grade, void* stream) {
+  int rc = check_system(m, sys);
+  if (rc) return rc;
+  if (!ainv || !grade) return mtp_fail(MTP_ERR_ARG, "null grade output or inverse active-set matrix");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = sys->n_atoms;
+  mtp_nlist use;
+  if ((rc = resolve_nlist(m, sys, nl, &use, s))) return rc;
+  const int na = m->ops.nalpha;
+  const long ld = std::max(1, std::min(m->chunk, std::max(n, 1)));
+  const long nchunks = ((long)n + ld - 1) / ld;
+  // per-chunk descriptor partials [chunk][na], then the descriptor itself
+  if ((rc = m->bvals.reserve((size_t)na * ld * sizeof(double))) ||
+      (rc = m->eatom.reserve((size_t)std::max(n, 1) * sizeof(double))) ||
+      (rc = m->dxi_part.reserve((size_t)(nchunks + 1) * na * sizeof(double))))
+    return rc;
+  double* bv = (double*)m->bvals.p;
+  double* part = (double*)m->dxi_part.p;
+  double* desc = descriptor ? descriptor : part + nchunks * na;
+  if (n > 0) {
+    long chunk = 0;
+    rc = run_energy_chain(m, sys, use, (double*)m->eatom.p, false, bv, s, [&](int, int cn) {
+      ProfScope ps(&m->prof, P_REDUCE, s);
+      launch_rowsum(bv, ld, 1, cn, na, part + chunk * na, 1, s);
+      ++chunk;
+    });
+    if (rc) return rc;
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_rowsum(part, 1, na, nchunks, na, desc, 1, s);
+  } else {
+    HIP_TRY(hipMemsetAsync(desc, 0, (size_t)na * sizeof(double), s));
+  }
+  {
+    ProfScope ps(&m->prof, P_GRADE, s);
+    launch_cfg_grade(desc, ainv, na, grade, s);
+  }
+  HIP_TRY(hipGetLastError());
+  if (m->grade_select > 0.0 || m->grade_break > 0.0) {
+    double gm = 0.0;
+    HIP_TRY(hipMemcpyAsync(&gm, grade, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (m->grade_break > 0.0 && gm > m->grade_break) return MTP_GRADE_BREAK;
+    if (m->grade_select > 0.0 && gm > m->grade_select) return MTP_GRADE_SELECT;
+  }
+  return MTP_OK;
+}
+
 extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double ebar,
                               const double* fbar, double* d_linear, double* d_radial, double* d_shift,
                               void* stream) {

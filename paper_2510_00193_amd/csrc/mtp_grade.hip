@@ -109,7 +109,31 @@ __global__ __launch_bounds__(1024) void k_max(const double* __restrict__ x, long
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// Configuration-mode grade: out[0] = max_k |sum_alpha b[alpha] ainv[alpha][k]| for one
+// descriptor b [na] (one workgroup; each thread owns columns k, reads rows of ainv coalesced).
+__global__ __launch_bounds__(1024) void k_cfg_grade(const double* __restrict__ b, const double* __restrict__ ainv,
+                                                    int na, double* __restrict__ out) {
+  __shared__ double sh[1024];
+  double m = 0.0;
+  for (int k = threadIdx.x; k < na; k += 1024) {
+    double v = 0.0;
+    for (int a = 0; a < na; ++a) v = fma(b[a], ainv[(long)a * na + k], v);
+    m = fmax(m, fabs(v));
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 }  // namespace
+
+void launch_cfg_grade(const double* b, const double* ainv, int na, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cfg_grade, dim3(1), dim3(1024), 0, s, b, ainv, na, out);
+}
 
 void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,
                   double* grade, hipStream_t s) {

@@ -120,5 +120,7 @@ void launch_species_grad_cfg(const int* species, const int* cfg, const double* e
 void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,
                   double* grade, hipStream_t s);
 void launch_max(const double* x, long n, double* out, hipStream_t s);
+// out[0] = max_k |(b . ainv)_k| for one descriptor b [na]
+void launch_cfg_grade(const double* b, const double* ainv, int na, double* out, hipStream_t s);
 
 }  // namespace mtp

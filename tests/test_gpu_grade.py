@@ -81,3 +81,44 @@ def test_grade_thresholds_and_chunks():
     assert out["status"] == 8
     out = _run(p, s, ainv, "fp64", grade_select=gmax * 4, grade_break=gmax * 8)
     assert out["status"] == 0
+
+
+def test_config_grade_matches_oracle_and_maxvol():
+    """Configuration mode: descriptor sum_i B_i and max |b Ainv| against the oracle on small
+    triclinic configurations; configurations whose oracle descriptors form A have grade 1;
+    thresholds return their status codes; an empty configuration has grade 0."""
+    from paper_2510_00193_amd import Potential
+    from helpers import small_batch
+    structs, p = small_batch(611, 19, 10, n_min=8, n_max=40)
+    model = om.Model.from_params(p)
+    n_alpha = len(model.basis)
+    desc = np.array([om.config_descriptor(om.energy_forces_virial(model, st)["B"].detach().numpy())
+                     for st in structs])
+    ainv = np.linalg.inv(desc[:n_alpha])
+    pot = Potential.from_params(p)
+    a_dev = torch.as_tensor(ainv, device="cuda")
+    for k, st in enumerate(structs):
+        print(f"[config grade] cfg {k} N={st.n_atoms}", flush=True)
+        out = pot.grade_config(torch.as_tensor(st.pos, device="cuda"), torch.as_tensor(st.species, device="cuda"),
+                               st.cell, a_dev)
+        torch.cuda.synchronize()
+        want = om.config_grade(desc[k][None, :], ainv)
+        got_desc = out["descriptor"].cpu().numpy()
+        assert np.max(np.abs(got_desc - desc[k])) / np.max(np.abs(desc[k])) < 1e-10
+        assert _grade_err(np.array([float(out["grade"].cpu())]), np.array([want])) < TOL_GRADE
+        if k < n_alpha:
+            assert abs(float(out["grade"].cpu()) - 1.0) < 1e-8
+    # thresholds on the last configuration (grade well above 1 for a configuration outside A)
+    st = structs[-1]
+    g = float(pot.grade_config(torch.as_tensor(st.pos, device="cuda"), torch.as_tensor(st.species, device="cuda"),
+                               st.cell, a_dev)["grade"].cpu())
+    from paper_2510_00193_amd import _lib
+    pot_sel = Potential.from_params(p, grade_select=0.5 * g)
+    pot_brk = Potential.from_params(p, grade_select=0.25 * g, grade_break=0.5 * g)
+    args = (torch.as_tensor(st.pos, device="cuda"), torch.as_tensor(st.species, device="cuda"), st.cell, a_dev)
+    assert pot_sel.grade_config(*args)["status"] == _lib.MTP_GRADE_SELECT
+    assert pot_brk.grade_config(*args)["status"] == _lib.MTP_GRADE_BREAK
+    empty = pot.grade_config(torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                             torch.zeros((0,), dtype=torch.int32, device="cuda"), np.eye(3) * 20.0, a_dev)
+    torch.cuda.synchronize()
+    assert float(empty["grade"].cpu()) == 0.0

@@ -263,13 +263,31 @@ def _emit_inner(w, lst, var):
 PREFETCH_DEPTH = int(os.environ.get("MTP_PREFETCH_DEPTH", "24"))
 
 
+def _locality_order(blocks):
+    """Contraction blocks reordered so that consecutive blocks share moment entries (each next
+    block has the largest overlap with the entries of the last three): re-reads of an entry
+    come soon after its first read and hit the cache.  The blocks are independent sums, so the
+    order is free."""
+    rem = list(blocks)
+    if not rem:
+        return rem
+    order = [max(rem, key=lambda b: (len(b.entries), -b.q))]
+    rem.remove(order[0])
+    while rem:
+        recent = set(e for b in order[-3:] for e in b.entries)
+        nxt = max(rem, key=lambda b: (len(set(b.entries) & recent), -len(b.entries), -b.q))
+        order.append(nxt)
+        rem.remove(nxt)
+    return order
+
+
 def _emit_components_forward(w: _W, prog: Program):
     """Connected contractions.  No block fences here: the blocks are independent and the
     scheduler interleaves them freely (their loads overlap the arithmetic of other blocks)."""
     w("template <class R, class MA>")
     w("static __device__ __forceinline__ void fwd(const MA& M, R* __restrict__ C) {")
     w.push()
-    for blk in prog.blocks:
+    for blk in _locality_order(prog.blocks):
         w(f"{{  // contraction {blk.q}")
         w.push()
         for e in blk.entries:
@@ -288,7 +306,7 @@ def _emit_components_reverse(w: _W, prog: Program, groups):
         w("template <class R, class MA, class CB>")
         w(f"static __device__ __forceinline__ void rev_g{gi}(const MA& M, const CB& Cb, R* __restrict__ mb) {{")
         w.push()
-        blocks = [blk for blk in prog.blocks if any(lo <= e < hi for e in blk.entries)]
+        blocks = _locality_order([blk for blk in prog.blocks if any(lo <= e < hi for e in blk.entries)])
         seq = [e for blk in blocks for e in blk.entries]   # every moment load, in program order
         depth = max(1, min(PREFETCH_DEPTH, len(seq)))
         for k in range(depth):

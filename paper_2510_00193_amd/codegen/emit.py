@@ -628,7 +628,7 @@ def _emit_components_forward_tangent(w: _W, prog: Program):
     w("template <class R, class MA>")
     w("static __device__ __forceinline__ void fwd_tan(const MA& M, const MA& Md, R* __restrict__ C, R* __restrict__ Cd) {")
     w.push()
-    for blk in prog.blocks:
+    for blk in _locality_order(prog.blocks):
         w(f"{{  // contraction {blk.q}")
         w.push()
         for e in blk.entries:
@@ -696,9 +696,7 @@ def _emit_components_reverse_tangent(w: _W, prog: Program, groups):
         w(f"static __device__ __forceinline__ void rev_tan_g{gi}(const MA& M, const MA& Md, const R* __restrict__ Cb,")
         w("    const R* __restrict__ Cbd, R* __restrict__ mbd) {")
         w.push()
-        for blk in prog.blocks:
-            if not any(lo <= e < hi for e in blk.entries):
-                continue
+        for blk in _locality_order([b for b in prog.blocks if any(lo <= e < hi for e in b.entries)]):
             w(f"{{  // contraction {blk.q}")
             w.push()
             w("MTP_BLOCK_FENCE();")

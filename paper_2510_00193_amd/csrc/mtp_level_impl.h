@@ -1,6 +1,6 @@
 // Level-templated MTP kernels.  A translation unit includes one generated level header
 // (struct LvXX with the straight-line program) and then this file, and instantiates the
-// launchers with MTP_DEFINE_LEVEL.
+// launchers with MTP_DEFINE_CHAIN / MTP_DEFINE_ADJ / MTP_DEFINE_ADJ_FWD / MTP_DEFINE_ADJ_REV.
 //
 // Every kernel maps one lane to one atom: the per-atom state (moments, contraction
 // outputs, adjoints) lives in registers with compile-time indices, the neighbour loop of

@@ -261,7 +261,7 @@ def test_param_vjp_matches_finite_differences():
     def target(radial, linear, shift):
         out = om.energy_forces_virial(model, s, nl, torch.as_tensor(radial), torch.as_tensor(linear),
                                       torch.as_tensor(shift))
-        return float(ebar * out["E"] + (out["F"] * torch.as_tensor(fbar)).sum())
+        return float((ebar * out["E"] + (out["F"] * torch.as_tensor(fbar)).sum()).detach())
 
     r0, l0, s0 = model.radial.numpy(), model.linear.numpy(), model.shift.numpy()
     for name, arr, got in (("linear", l0, dxi), ("radial", r0, dc), ("shift", s0, ds)):

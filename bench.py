@@ -127,7 +127,11 @@ def section_fp32(s, params, pos, sp, ref, steps):
     pot = Potential.from_params(params, precision="fp32")
     nl = pot.neighbors(pos, sp, s.cell)
     dt_eval = _timeit(lambda: pot.compute(pos, sp, s.cell, nlist=nl), steps)
-    dt_full = _timeit(lambda: pot.compute(pos, sp, s.cell), steps)
+    pot.profile(True)
+    pot.profile_reset()
+    dt_full = _timeit(lambda: pot.compute(pos, sp, s.cell), steps, warmup=0)
+    prof = pot.profile_read()
+    pot.profile(False)
     out = pot.compute(pos, sp, s.cell, nlist=nl)
     torch.cuda.synchronize()
 
@@ -137,6 +141,7 @@ def section_fp32(s, params, pos, sp, ref, steps):
 
     return {"value": s.n_atoms / dt_full, "unit": "atom-steps/s", "ms_per_step": dt_full * 1e3,
             "eval_only_atom_steps_per_s": s.n_atoms / dt_eval,
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
             "rel_err_vs_fp64": {"E": rel(out["energy"].reshape(1), ref["energy"].reshape(1)),
                                 "F": rel(out["forces"], ref["forces"]), "W": rel(out["virial"], ref["virial"])}}
 

@@ -37,6 +37,7 @@ struct mtp_batch {
   const double* pos = nullptr;
   const int* species = nullptr;
   DevBuf atom_off, cfg, cells, cinv, reach, off, nj, shift, rev, perm;
+  DevBuf zpair;                    // neighbour species per pair (fixed with the lists)
   std::vector<int> h_off;          // host copy of the CSR offsets (neighbour counts)
   // workspace
   DevBuf eatom, watom, g, fown, forces, energy, virial, mom, cbar, mbar, mdot, cbard, mbard, xout, dxi_part,
@@ -141,6 +142,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
   a.cfg = (const int*)b->cfg.p;
   a.perm = (const int*)b->perm.p;
   a.ebar = nullptr;
+  a.zpair = b->zpair.p ? (const unsigned char*)b->zpair.p : nullptr;
   a.sa = 2.0 / (m->rcut - m->rmin);
   a.sb = -(m->rmin + m->rcut) / (m->rcut - m->rmin);
   a.rcut = m->rcut;
@@ -316,6 +318,13 @@ int mtp_batch_create(mtp_model* m, int n_cfg, const int* atom_off, const double*
                                : mtp_fail(MTP_ERR_CELL, "an image shift does not fit in int8");
   }
   b->npairs = total;
+  if (m->nsp > 1 && total > 0) {
+    if ((rc = b->zpair.reserve((size_t)total))) {
+      delete b;
+      return mtp_fail(rc, "allocating the pair species failed");
+    }
+    launch_pair_species(nj, species, m->nsp, total, (unsigned char*)b->zpair.p, s);
+  }
   b->h_off.resize(n + 1);
   if (hipMemcpy(b->h_off.data(), b->off.p, (n + 1) * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
     delete b;

@@ -168,7 +168,20 @@ __global__ __launch_bounds__(kNT) void k_species_grad_cfg(const int* __restrict_
   if (threadIdx.x == 0) out[t] = v;
 }
 
+__global__ void k_pair_species(const int* __restrict__ nj, const int* __restrict__ species, int nsp,
+                               long long npairs, unsigned char* __restrict__ zp) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npairs) zp[p] = (unsigned char)clamp_species(species[nj[p]], nsp);
+}
+
 }  // namespace
+
+void launch_pair_species(const int* nj, const int* species, int nsp, long long npairs, unsigned char* zp,
+                         hipStream_t s) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_pair_species, dim3((unsigned)((npairs + kNT - 1) / kNT)), dim3(kNT), 0, s, nj, species, nsp,
+                     npairs, zp);
+}
 
 void launch_segsum(const double* x, long stride, const int* seg_off, int nseg, int ncomp, double* out,
                    long os, hipStream_t s) {

@@ -23,6 +23,7 @@ struct SysArgs {
   const int* cfg;         // [N] configuration of each atom (batches), or null
   const int* perm;        // [N] processing order: lane k of the sweep takes atom perm[k], or null
   const double* ebar;     // [n_cfg] per-configuration energy cotangent (batches), or null
+  const unsigned char* zpair;  // [P] species of each pair's neighbour (clamped), or null
   double sa, sb, rcut;    // u = sa r + sb
   int nsp, nmu, ncheb;
 };
@@ -120,6 +121,9 @@ void launch_species_grad_cfg(const int* species, const int* cfg, const double* e
 void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,
                   double* grade, hipStream_t s);
 void launch_max(const double* x, long n, double* out, hipStream_t s);
+// zp[p] = species of neighbour nj[p], clamped to [0, nsp)
+void launch_pair_species(const int* nj, const int* species, int nsp, long long npairs, unsigned char* zp,
+                         hipStream_t s);
 // out[0] = max_k |(b . ainv)_k| for one descriptor b [na]
 void launch_cfg_grade(const double* b, const double* ainv, int na, double* out, hipStream_t s);
 

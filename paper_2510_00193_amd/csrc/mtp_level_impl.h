@@ -406,13 +406,22 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
   const double fix = fbar[3 * i], fiy = fbar[3 * i + 1], fiz = fbar[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
   const int p0 = live ? a.off[i] : 0, p1 = live ? a.off[i + 1] : 0;
+  // species of the neighbour of pair p (precomputed bytes when available)
+  auto zj_of = [&](int p) -> int {
+    return a.zpair ? (int)a.zpair[p] : clamp_species(a.species[a.nj[p]], a.nsp);
+  };
   for (int t = 0; t < a.nsp; ++t) {
     double acc[NMU * kMaxCheb];
 #pragma unroll
     for (int k = 0; k < NMU * kMaxCheb; ++k) acc[k] = 0.0;
-    for (int p = p0; p < p1; ++p) {
+    // each lane steps to its own next pair of species t, so the wave runs the pair body
+    // max over lanes (not the row length) times per species
+    int p = p0;
+    for (;;) {
+      while (p < p1 && zj_of(p) != t) ++p;
+      if (!__any(p < p1)) break;
+      if (p >= p1) continue;
       const int j = a.nj[p];
-      if (clamp_species(a.species[j], a.nsp) != t) continue;
       int n1, n2, n3;
       unpack_shift(a.shift[p], n1, n2, n3);
       double dx, dy, dz;
@@ -456,6 +465,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 #pragma unroll
         for (int mu = 0; mu < NMU; ++mu) acc[mu * kMaxCheb + bq] = fma(q, X[mu], fma(qp, Y[mu], acc[mu * kMaxCheb + bq]));
       }
+      ++p;
     }
     for (int sp = 0; sp < a.nsp; ++sp) {
       for (int mu = 0; mu < NMU; ++mu)

@@ -63,6 +63,40 @@ def entry_groups(prog: Program, n_groups):
     return [(bounds[k], bounds[k + 1]) for k in range(len(bounds) - 1)]
 
 
+# Most moment entries one adjoint pair group holds: the pair kernel of the parameter adjoint
+# keeps the adjoint and its tangent of every entry of its group in registers, next to the
+# per-lane radial-gradient sums of the group's mu values.
+ADJ_GROUP_CAP = 48
+
+
+def adj_entry_groups(prog: Program, cap=ADJ_GROUP_CAP):
+    """Split the flat moment layout (mu-major) into contiguous ranges of at most cap entries
+    for the adjoint pair kernel: a mu segment longer than cap is cut into equal parts, and
+    consecutive short segments share a range while they fit."""
+    mus = [it[0] for it in prog.layout.items]
+    assert mus == sorted(mus), "the moment layout is mu-major"
+    segs = []
+    for e, mu in enumerate(mus):
+        if segs and segs[-1][2] == mu:
+            segs[-1][1] = e + 1
+        else:
+            segs.append([e, e + 1, mu])
+    out, open_range = [], False  # open_range: the last range holds whole short segments
+    for lo, hi, _ in segs:
+        n = hi - lo
+        if n > cap:
+            k = -(-n // cap)
+            cuts = [lo + round(q * n / k) for q in range(k + 1)]
+            out += [(cuts[q], cuts[q + 1]) for q in range(k)]
+            open_range = False
+        elif open_range and out[-1][1] - out[-1][0] + n <= cap:
+            out[-1] = (out[-1][0], hi)
+        else:
+            out.append((lo, hi))
+            open_range = True
+    return out
+
+
 def _ref(r, mvar="me"):
     kind, k = r
     if kind == "m":
@@ -452,6 +486,7 @@ def _emit_dispatchers(w: _W, n_groups: int):
 def emit_level(level: int, n_groups: int = 1) -> str:
     prog = build_program(level)
     groups = entry_groups(prog, n_groups)
+    agroups = adj_entry_groups(prog)
     w = _W()
     w(f"// Generated MTP level-{level} program.  Do not edit; produced by codegen/emit.py.")
     w("#pragma once")
@@ -467,6 +502,12 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     w(f"static constexpr int TRIPLES = {prog.triple_count()};")
     w("static constexpr int GROUP_LO[NGROUP] = {" + ", ".join(str(g[0]) for g in groups) + "};")
     w("static constexpr int GROUP_HI[NGROUP] = {" + ", ".join(str(g[1]) for g in groups) + "};")
+    # ranges of the adjoint pair kernel and the mu values [AMU_LO, AMU_HI] each one touches
+    w(f"static constexpr int NAGROUP = {len(agroups)};")
+    w("static constexpr int AGROUP_LO[NAGROUP] = {" + ", ".join(str(g[0]) for g in agroups) + "};")
+    w("static constexpr int AGROUP_HI[NAGROUP] = {" + ", ".join(str(g[1]) for g in agroups) + "};")
+    w("static constexpr int AMU_LO[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[0]][0]) for g in agroups) + "};")
+    w("static constexpr int AMU_HI[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[1] - 1][0]) for g in agroups) + "};")
     w("// flat moment layout: (mu, a, b, c) of component e")
     w("static constexpr int ENTRIES[NMOM][4] = {" + ", ".join("{%d, %d, %d, %d}" % it for it in prog.layout.items) + "};")
     # a! b! c! of each entry: pair_grad takes the moment adjoints scaled by it
@@ -477,7 +518,7 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     _emit_components_reverse(w, prog, groups)
     _emit_products(w, prog)
     _emit_dispatchers(w, len(groups))
-    emit_tangent_parts(w, prog, groups)
+    emit_tangent_parts(w, prog, groups, agroups)
     w.pop()
     w("};")
     return w.text()
@@ -530,19 +571,53 @@ def _emit_tangent_pair_functions(w: _W, prog: Program, groups):
                 w(f"md[{e - lo}] = fma(f[{mu}], {_tmono_name(abc)}, fma(fp[{mu}] * rdot, {_mono_name(abc)}, md[{e - lo}]));")
         w.pop()
         w("}")
-        # ---------------- per-mu sums of the adjoint pair term
-        # S_mu = sum_e mb_e mono_e ;  A_mu = sum_e (mbd_e mono_e + mb_e dmono_e)
+
+
+def _emit_adj_pair_functions(w: _W, prog: Program, agroups):
+    """Per-mu sums of the adjoint pair term over one adjoint group:
+    S_mu = sum_e mb_e mono_e ;  A_mu = sum_e (mbd_e mono_e + mb_e dmono_e)."""
+    items = prog.layout.items
+    for gi, (lo, hi) in enumerate(agroups):
+        ents = list(range(lo, hi))
+        order = sorted({items[e][1:] for e in ents}, key=lambda t: (t[0] + t[1] + t[2], -t[0], -t[1]))
+        by_mono = defaultdict(list)
+        for e in ents:
+            mu, a, b, c = items[e]
+            by_mono[(a, b, c)].append((e, mu))
+        w(f"// adjoint group {gi}: entries [{lo}, {hi})")
         w("template <class R>")
         w(f"static __device__ __forceinline__ void adj_pair_g{gi}(const R* __restrict__ mb, const R* __restrict__ mbd,")
         w("    R x, R y, R z, R ex, R ey, R ez, R* __restrict__ S, R* __restrict__ A) {")
         w.push()
+        # ADJ_CHAINS independent partial sums per mu shorten the dependent fma chains
+        mus = sorted({items[e][0] for e in ents})
+        nch = {mu: min(ADJ_CHAINS, sum(1 for e in ents if items[e][0] == mu)) for mu in mus}
+        for mu in mus:
+            w(" ".join(f"R s{mu}_{k} = R(0), a{mu}_{k} = R(0);" for k in range(nch[mu])))
         _emit_monomials_with_tangent(w, order)
+        seen = defaultdict(int)
         for abc in order:
             for e, mu in by_mono[abc]:
-                w(f"S[{mu}] = fma(mb[{e - lo}], {_mono_name(abc)}, S[{mu}]);")
-                w(f"A[{mu}] = fma(mbd[{e - lo}], {_mono_name(abc)}, fma(mb[{e - lo}], {_tmono_name(abc)}, A[{mu}]));")
+                k = seen[mu] % nch[mu]
+                seen[mu] += 1
+                w(f"s{mu}_{k} = fma(mb[{e - lo}], {_mono_name(abc)}, s{mu}_{k});")
+                w(f"a{mu}_{k} = fma(mbd[{e - lo}], {_mono_name(abc)}, fma(mb[{e - lo}], {_tmono_name(abc)}, a{mu}_{k}));")
+        for mu in mus:
+            w(f"S[{mu}] += " + _pair_sum([f"s{mu}_{k}" for k in range(nch[mu])]) + ";")
+            w(f"A[{mu}] += " + _pair_sum([f"a{mu}_{k}" for k in range(nch[mu])]) + ";")
         w.pop()
         w("}")
+
+
+ADJ_CHAINS = 4
+
+
+def _pair_sum(names):
+    """Balanced sum expression of names."""
+    if len(names) == 1:
+        return names[0]
+    h = len(names) // 2
+    return f"({_pair_sum(names[:h])} + {_pair_sum(names[h:])})"
 
 
 def _tmono_name(abc):
@@ -764,7 +839,7 @@ def _emit_products_tangent(w: _W, prog: Program):
     w("}")
 
 
-def _emit_tangent_dispatchers(w: _W, n_groups: int):
+def _emit_tangent_dispatchers(w: _W, n_groups: int, n_agroups: int):
     sigs = (
         ("tan_moments", "R* __restrict__ md, const R* __restrict__ f, const R* __restrict__ fp, R x, R y, R z, "
                         "R ex, R ey, R ez, R rdot", "md, f, fp, x, y, z, ex, ey, ez, rdot", "class R", "<R>"),
@@ -777,16 +852,17 @@ def _emit_tangent_dispatchers(w: _W, n_groups: int):
         w(f"template <int G, {tparams}>")
         w(f"static __device__ __forceinline__ void {name}({params}) {{")
         w.push()
-        for g in range(n_groups):
+        for g in range(n_agroups if name == "adj_pair" else n_groups):
             kw = "if constexpr" if g == 0 else "else if constexpr"
             w(f"{kw} (G == {g}) {name}_g{g}{targs}({args});")
         w.pop()
         w("}")
 
 
-def emit_tangent_parts(w: _W, prog: Program, groups):
+def emit_tangent_parts(w: _W, prog: Program, groups, agroups):
     _emit_tangent_pair_functions(w, prog, groups)
+    _emit_adj_pair_functions(w, prog, agroups)
     _emit_components_forward_tangent(w, prog)
     _emit_components_reverse_tangent(w, prog, groups)
     _emit_products_tangent(w, prog)
-    _emit_tangent_dispatchers(w, len(groups))
+    _emit_tangent_dispatchers(w, len(groups), len(agroups))

@@ -578,7 +578,7 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
   const int nchunks = (n + chunk - 1) / chunk;
   long nblk = 0;
   for (int i0 = 0; i0 < n; i0 += chunk) nblk += (std::min(chunk, n - i0) + kLaneBlockHost - 1) / kLaneBlockHost;
-  const long nparts = nblk * L.ngroup;
+  const long nparts = nblk * L.adj.nagroup;
   if ((rc = m->mom.reserve((size_t)L.nmom * ld * 8)) || (rc = m->cbar.reserve((size_t)L.ncomp * ld * 8)) ||
       (rc = m->mbar.reserve((size_t)L.nmom * ld * 8)) || (rc = m->mdot.reserve((size_t)L.nmom * ld * 8)) ||
       (rc = m->cbard.reserve((size_t)L.ncomp * ld * 8)) || (rc = m->mbard.reserve((size_t)L.nmom * ld * 8)) ||
@@ -625,7 +625,7 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
       ProfScope ps(&m->prof, P_TANGENT, s);
       L.adj.tan_reverse[g](mom, mdot, ld, cn, cbar, cbard, mbard, s);
     }
-    for (int g = 0; g < L.ngroup; ++g) {
+    for (int g = 0; g < L.adj.nagroup; ++g) {
       ProfScope ps(&m->prof, P_ADJ_PAIRS, s);
       L.adj.adj_pairs(g, a, fbar, i0, cn, mbar, mbard, ld, ebar, cpart + part * K, s);
       part += cblk;

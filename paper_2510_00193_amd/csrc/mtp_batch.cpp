@@ -93,7 +93,7 @@ static int reserve_run(mtp_batch* b) {
       (rc = b->mbar.reserve(L.nmom * ld * 8)) || (rc = b->mdot.reserve(L.nmom * ld * 8)) ||
       (rc = b->cbard.reserve(L.ncomp * ld * 8)) || (rc = b->mbard.reserve(L.nmom * ld * 8)) ||
       (rc = b->xout.reserve(L.nalpha * ld * 8)) || (rc = b->dxi_part.reserve(L.nalpha * nchunks * 8)) ||
-      (rc = b->cpart.reserve(nblk * L.ngroup * K * 8)) || (rc = b->wpart.reserve(nblk * 6 * 8)) ||
+      (rc = b->cpart.reserve(nblk * L.adj.nagroup * K * 8)) || (rc = b->wpart.reserve(nblk * 6 * 8)) ||
       (rc = b->ebar_cfg.reserve(b->ncfg * 8)) || (rc = b->fbar.reserve(3 * n * 8)) ||
       (rc = b->parts.reserve((b->ncfg + n) * 8)))
     return rc;
@@ -236,7 +236,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
       L.adj.tan_reverse[gi]((const double*)b->mom.p, (const double*)b->mdot.p, ld, cn, (const double*)b->cbar.p,
                     (const double*)b->cbard.p, (double*)b->mbard.p, s);
     }
-    for (int gi = 0; gi < L.ngroup; ++gi) {
+    for (int gi = 0; gi < L.adj.nagroup; ++gi) {
       ProfScope ps(&m->prof, P_ADJ_PAIRS, s);
       L.adj.adj_pairs(gi, a, fbar, (int)i0, cn, (const double*)b->mbar.p, (const double*)b->mbard.p, ld, 0.0,
                   cpart + part * KR, s);

@@ -54,8 +54,11 @@ struct AdjOps {
   // one launcher per moment group (compiled in separate units)
   void (*tan_reverse[kMaxGroups])(const double* m, const double* md, long ld, int n, const double* cb,
                                   const double* cbd, double* mbd, hipStream_t s);
+  // grp is one of the nagroup adjoint groups (moment ranges sized for the pair kernel's
+  // registers, independent of the chain's groups)
   void (*adj_pairs)(int grp, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                     const double* mbd, long ld, double ebar, double* cpart, hipStream_t s);
+  int nagroup;
 };
 
 // Launchers of one compiled level (assembled from the level's translation units).

@@ -379,8 +379,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Radial-coefficient gradient: per pair (i, j) with species (s, t),
 //   dc[s][t][mu][b] += Q_b (ebar S_mu - A_mu) - Q'_b (rhat . delta) S_mu,
 // accumulated per lane for one neighbour species at a time and summed over the wave with a
-// fixed butterfly; one partial per (workgroup, s, t) lands in cpart.
-template <class L, int G>
+// fixed butterfly; one partial per (workgroup, s, t) lands in cpart. G is an adjoint group: a
+// moment range small enough that its adjoints, their tangents and the sums of its mu values
+// [AMU_LO, AMU_HI] stay in registers; the partial rows of the other mu values are written as
+// zeros. NC is the compile-time Chebyshev count (0: runtime count up to kMaxCheb); every index
+// into the accumulators is a compile-time constant.
+template <class L, int G, int NC>
 __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const double* __restrict__ fbar,
                                                           int i0, int n,
                                                           const double* __restrict__ mbar,
@@ -388,9 +392,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
                                                           double ebar, double* __restrict__ cpart) {
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
-  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
-  constexpr int NMU = L::NMU;
-  const int nq = a.ncheb;
+  constexpr int LO = L::AGROUP_LO[G], HI = L::AGROUP_HI[G], NG = HI - LO;
+  constexpr int NMU = L::NMU, MLO = L::AMU_LO[G], MHI = L::AMU_HI[G], NM = MHI - MLO + 1;
+  constexpr int NQ = NC > 0 ? NC : kMaxCheb;
+  const int nq = NC > 0 ? NC : a.ncheb;
   const bool live = li < n;
   const int i = atom_at(a, i0 + (live ? li : 0));
   double H[9];
@@ -411,9 +416,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
     return a.zpair ? (int)a.zpair[p] : clamp_species(a.species[a.nj[p]], a.nsp);
   };
   for (int t = 0; t < a.nsp; ++t) {
-    double acc[NMU * kMaxCheb];
+    double acc[NM * NQ];
 #pragma unroll
-    for (int k = 0; k < NMU * kMaxCheb; ++k) acc[k] = 0.0;
+    for (int k = 0; k < NM * NQ; ++k) acc[k] = 0.0;
     // each lane steps to its own next pair of species t, so the wave runs the pair body
     // max over lanes (not the row length) times per species
     int p = p0;
@@ -434,18 +439,18 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 #pragma unroll
       for (int mu = 0; mu < NMU; ++mu) S[mu] = A[mu] = 0.0;
       L::template adj_pair<G>(mb, mbd, dx, dy, dz, ex, ey, ez, S, A);
-      double X[NMU], Y[NMU];
+      double X[NM], Y[NM];
 #pragma unroll
-      for (int mu = 0; mu < NMU; ++mu) {
-        X[mu] = fma(ebar, S[mu], -A[mu]);
-        Y[mu] = -rdot * S[mu];
+      for (int k = 0; k < NM; ++k) {
+        X[k] = fma(ebar, S[MLO + k], -A[MLO + k]);
+        Y[k] = -rdot * S[MLO + k];
       }
       // Q_b = T_b(u) w^2, Q'_b = sa T'_b(u) w^2 - 2 T_b(u) w
       const double u = fma(a.sa, r, a.sb), w = a.rcut - r, w2 = w * w;
       double t2 = 1.0, t1 = u, d2 = 0.0, d1 = 1.0;
 #pragma unroll
-      for (int bq = 0; bq < kMaxCheb; ++bq) {
-        if (bq >= nq) break;
+      for (int bq = 0; bq < NQ; ++bq) {
+        if (NC == 0 && bq >= nq) break;
         double T, D;
         if (bq == 0) {
           T = 1.0;
@@ -463,16 +468,23 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
         }
         const double q = T * w2, qp = fma(a.sa * w2, D, -2.0 * w * T);
 #pragma unroll
-        for (int mu = 0; mu < NMU; ++mu) acc[mu * kMaxCheb + bq] = fma(q, X[mu], fma(qp, Y[mu], acc[mu * kMaxCheb + bq]));
+        for (int k = 0; k < NM; ++k) acc[k * NQ + bq] = fma(q, X[k], fma(qp, Y[k], acc[k * NQ + bq]));
       }
       ++p;
     }
     for (int sp = 0; sp < a.nsp; ++sp) {
-      for (int mu = 0; mu < NMU; ++mu)
-        for (int bq = 0; bq < nq; ++bq) {
-          const double v = wave_sum((live && zi == sp) ? acc[mu * kMaxCheb + bq] : 0.0);
-          if (threadIdx.x == 0)
-            cpart[(long)b * a.nsp * a.nsp * NMU * nq + ((sp * a.nsp + t) * NMU + mu) * nq + bq] = v;
+      double* dst = cpart + (long)b * a.nsp * a.nsp * NMU * nq + (long)(sp * a.nsp + t) * NMU * nq;
+      for (int k = threadIdx.x; k < NMU * nq; k += kLaneBlock) {
+        const int mu = k / nq;
+        if (mu < MLO || mu > MHI) dst[k] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < NM; ++k)
+#pragma unroll
+        for (int bq = 0; bq < NQ; ++bq) {
+          if (NC == 0 && bq >= nq) break;
+          const double v = wave_sum((live && zi == sp) ? acc[k * NQ + bq] : 0.0);
+          if (threadIdx.x == 0) dst[(MLO + k) * nq + bq] = v;
         }
     }
   }
@@ -597,8 +609,15 @@ struct AdjImpl {
   static void adj_pairs_g(const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                           const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
     const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-    hipLaunchKernelGGL((k_adj_pairs<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
-                       ebar, cpart);
+    if (a.ncheb == 8)
+      hipLaunchKernelGGL((k_adj_pairs<L, G, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+                         ebar, cpart);
+    else if (a.ncheb == 10)
+      hipLaunchKernelGGL((k_adj_pairs<L, G, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+                         ebar, cpart);
+    else
+      hipLaunchKernelGGL((k_adj_pairs<L, G, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+                         ebar, cpart);
   }
   template <size_t... Gs>
   static void adj_pairs_d(int g, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
@@ -608,12 +627,13 @@ struct AdjImpl {
   }
   static void adj_pairs(int g, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                         const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
-    adj_pairs_d(g, a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s, std::make_index_sequence<L::NGROUP>{});
+    adj_pairs_d(g, a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s, std::make_index_sequence<L::NAGROUP>{});
   }
   static AdjOps ops() {
     AdjOps o{};
     o.tan_moments = &tan_moments;
     o.adj_pairs = &adj_pairs;
+    o.nagroup = L::NAGROUP;
     return o;
   }
 };

@@ -76,6 +76,16 @@ static void tan_group(const std::vector<double>& d, const std::vector<double>& d
   }
 }
 
+// every adjoint group of the level, each over its own moment range
+template <int G>
+static void adj_pair_groups(const double* mb, const double* mbd, double x, double y, double z, double ex,
+                            double ey, double ez, double* S, double* A) {
+  if constexpr (G < L::NAGROUP) {
+    L::adj_pair<G>(mb + L::AGROUP_LO[G], mbd + L::AGROUP_LO[G], x, y, z, ex, ey, ez, S, A);
+    adj_pair_groups<G + 1>(mb, mbd, x, y, z, ex, ey, ez, S, A);
+  }
+}
+
 int main() {
   const int np = 6;
   std::vector<double> d(3 * np), dl(3 * np);
@@ -227,16 +237,7 @@ int main() {
     for (int e = 0; e < L::NMOM; ++e) { mb[e] = unif(-1, 1); mbd[e] = unif(-1, 1); }
     double x = d[0], y = d[1], z = d[2], ex = dl[0], ey = dl[1], ez = dl[2];
     std::vector<double> S(L::NMU, 0.0), A(L::NMU, 0.0), Sw(L::NMU, 0.0), Aw(L::NMU, 0.0);
-    for (int g = 0; g < L::NGROUP; ++g) {
-      const int lo = L::GROUP_LO[g];
-      if (g == 0) L::adj_pair<0>(mb.data() + lo, mbd.data() + lo, x, y, z, ex, ey, ez, S.data(), A.data());
-#if MTP_NGROUP > 1
-      if (g == 1) L::adj_pair<1>(mb.data() + lo, mbd.data() + lo, x, y, z, ex, ey, ez, S.data(), A.data());
-#endif
-#if MTP_NGROUP > 2
-      if (g == 2) L::adj_pair<2>(mb.data() + lo, mbd.data() + lo, x, y, z, ex, ey, ez, S.data(), A.data());
-#endif
-    }
+    adj_pair_groups<0>(mb.data(), mbd.data(), x, y, z, ex, ey, ez, S.data(), A.data());
     for (int e = 0; e < L::NMOM; ++e) {
       const int mu = L::ENTRIES[e][0], a = L::ENTRIES[e][1], b = L::ENTRIES[e][2], c = L::ENTRIES[e][3];
       const double mono = std::pow(x, a) * std::pow(y, b) * std::pow(z, c);

@@ -295,6 +295,9 @@ def _emit_inner(w, lst, var):
 # issues the load that many positions ahead, so the global-memory latency of one block is
 # covered by the arithmetic of the blocks before it.
 PREFETCH_DEPTH = int(os.environ.get("MTP_PREFETCH_DEPTH", "24"))
+# the same for the tangent of the reverse program (which loads moments, their tangents and
+# the contraction adjoints with their tangents)
+TAN_PREFETCH_DEPTH = int(os.environ.get("MTP_TAN_PREFETCH_DEPTH", "24"))
 
 
 def _locality_order(blocks):
@@ -767,17 +770,31 @@ def _emit_block_reverse_tangent(w: _W, blk, lo, hi):
 
 def _emit_components_reverse_tangent(w: _W, prog: Program, groups):
     for gi, (lo, hi) in enumerate(groups):
-        w("template <class R, class MA>")
-        w(f"static __device__ __forceinline__ void rev_tan_g{gi}(const MA& M, const MA& Md, const R* __restrict__ Cb,")
-        w("    const R* __restrict__ Cbd, R* __restrict__ mbd) {")
+        w("template <class R, class MA, class CB>")
+        w(f"static __device__ __forceinline__ void rev_tan_g{gi}(const MA& M, const MA& Md, const CB& Cb,")
+        w("    const CB& Cbd, R* __restrict__ mbd) {")
         w.push()
-        for blk in _locality_order([b for b in prog.blocks if any(lo <= e < hi for e in b.entries)]):
+        blocks = _locality_order([b for b in prog.blocks if any(lo <= e < hi for e in b.entries)])
+        # every load of the program in order (moments, their tangents, then the block's adjoint
+        # pair), kept TAN_PREFETCH_DEPTH ahead across the fenced blocks
+        seq = []
+        for blk in blocks:
+            seq += [(f"me{e}", f"M({e})") for e in blk.entries] + [(f"mde{e}", f"Md({e})") for e in blk.entries]
+            seq += [("cb", f"Cb[{blk.q}]"), ("cbd", f"Cbd[{blk.q}]")]
+        depth = max(1, min(TAN_PREFETCH_DEPTH, len(seq)))
+        for k in range(depth):
+            w(f"R pf{k} = {seq[k][1]};")
+        pos = 0
+        for blk in blocks:
             w(f"{{  // contraction {blk.q}")
             w.push()
             w("MTP_BLOCK_FENCE();")
-            for e in blk.entries:
-                w(f"const R me{e} = M({e}), mde{e} = Md({e});")
-            w(f"const R cb = Cb[{blk.q}], cbd = Cbd[{blk.q}];")
+            for _ in range(2 * len(blk.entries) + 2):
+                slot = pos % depth
+                w(f"const R {seq[pos][0]} = pf{slot};")
+                if pos + depth < len(seq):
+                    w(f"pf{slot} = {seq[pos + depth][1]};")
+                pos += 1
             _emit_block_forward_tangent(w, blk, with_output=False)
             for k in range(blk.n_temp):
                 w(f"R tb{k} = R(0), tbd{k} = R(0);")
@@ -845,8 +862,8 @@ def _emit_tangent_dispatchers(w: _W, n_groups: int, n_agroups: int):
                         "R ex, R ey, R ez, R rdot", "md, f, fp, x, y, z, ex, ey, ez, rdot", "class R", "<R>"),
         ("adj_pair", "const R* __restrict__ mb, const R* __restrict__ mbd, R x, R y, R z, R ex, R ey, R ez, "
                      "R* __restrict__ S, R* __restrict__ A", "mb, mbd, x, y, z, ex, ey, ez, S, A", "class R", "<R>"),
-        ("rev_tan", "const MA& M, const MA& Md, const R* __restrict__ Cb, const R* __restrict__ Cbd, "
-                    "R* __restrict__ mbd", "M, Md, Cb, Cbd, mbd", "class R, class MA", "<R, MA>"),
+        ("rev_tan", "const MA& M, const MA& Md, const CB& Cb, const CB& Cbd, "
+                    "R* __restrict__ mbd", "M, Md, Cb, Cbd, mbd", "class R, class MA, class CB", "<R, MA, CB>"),
     )
     for name, params, args, tparams, targs in sigs:
         w(f"template <int G, {tparams}>")

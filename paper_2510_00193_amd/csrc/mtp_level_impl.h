@@ -25,6 +25,18 @@ struct GlobalMoments {
   __device__ __forceinline__ R operator()(int e) const { return p[(long)e * ld]; }
 };
 
+// Per-lane vector read from a [component][atom] array in global memory, one load per use.
+template <class R>
+struct GlobalVector {
+  const R* __restrict__ p;
+  long ld;
+  __device__ __forceinline__ R operator[](int q) const { return p[(long)q * ld]; }
+};
+
+// Contraction-adjoint vectors longer than this are read from memory where a block needs them
+// instead of being loaded into registers up front (which spills at the largest levels).
+constexpr int kRegComps = 64;
+
 // Per-lane vector held in LDS in [component][lane] layout (conflict-free across a wave).
 template <class R>
 struct LaneVector {
@@ -165,13 +177,17 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_rev(const R* __restrict_
   if (li >= n) return;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   GlobalMoments<R> M{mom + li, ld};
-  R Cb[L::NCOMP];
-#pragma unroll
-  for (int q = 0; q < L::NCOMP; ++q) Cb[q] = cbar[(long)q * ld + li];
   R mb[NG];
 #pragma unroll
   for (int e = 0; e < NG; ++e) mb[e] = R(0);
-  L::template rev<G>(M, Cb, mb);
+  if constexpr (L::NCOMP > kRegComps) {
+    L::template rev<G>(M, GlobalVector<R>{cbar + li, ld}, mb);
+  } else {
+    R Cb[L::NCOMP];
+#pragma unroll
+    for (int q = 0; q < L::NCOMP; ++q) Cb[q] = cbar[(long)q * ld + li];
+    L::template rev<G>(M, Cb, mb);
+  }
 #pragma unroll
   for (int e = 0; e < NG; ++e) mbar[(long)(LO + e) * ld + li] = mb[e];
 }
@@ -356,16 +372,20 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_reverse(const double* __rest
   if (li >= n) return;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   GlobalMoments<double> M{mom + li, ld}, Md{mdot + li, ld};
-  double Cb[L::NCOMP], Cbd[L::NCOMP];
-#pragma unroll
-  for (int q = 0; q < L::NCOMP; ++q) {
-    Cb[q] = cbar[(long)q * ld + li];
-    Cbd[q] = cbard[(long)q * ld + li];
-  }
   double mbd[NG];
 #pragma unroll
   for (int e = 0; e < NG; ++e) mbd[e] = 0.0;
-  L::template rev_tan<G>(M, Md, Cb, Cbd, mbd);
+  if constexpr (L::NCOMP > kRegComps) {
+    L::template rev_tan<G>(M, Md, GlobalVector<double>{cbar + li, ld}, GlobalVector<double>{cbard + li, ld}, mbd);
+  } else {
+    double Cb[L::NCOMP], Cbd[L::NCOMP];
+#pragma unroll
+    for (int q = 0; q < L::NCOMP; ++q) {
+      Cb[q] = cbar[(long)q * ld + li];
+      Cbd[q] = cbard[(long)q * ld + li];
+    }
+    L::template rev_tan<G>(M, Md, Cb, Cbd, mbd);
+  }
 #pragma unroll
   for (int e = 0; e < NG; ++e) mbard[(long)(LO + e) * ld + li] = mbd[e];
 }

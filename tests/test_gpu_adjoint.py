@@ -63,3 +63,11 @@ def test_vjp_thin_cells_three_species():
     rng = np.random.default_rng(3)
     for k, s in enumerate(structs):
         _compare(p, s, -0.3, rng.normal(size=(s.n_atoms, 3)), f"triclinic-{k}")
+
+
+def test_vjp_level14_runtime_chebyshev_count():
+    """Level 14 splits the moment layout into three adjoint ranges, one of which holds several
+    mu values; 6 Chebyshev functions take the runtime-count form of the pair kernels."""
+    s, p = small_lattice(904, (3, 3, 3), 3.16, 0.08, 14, 2, n_cheb=6)
+    rng = np.random.default_rng(4)
+    _compare(p, s, 1.3, rng.normal(size=(s.n_atoms, 3)), "L14-ncheb6")

@@ -343,7 +343,8 @@ SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist
   a.cfg = nullptr;
   a.perm = nullptr;
   a.ebar = nullptr;
-  a.zpair = nullptr;
+  a.plink = nullptr;
+  a.pfirst = nullptr;
   a.sa = 2.0 / (m->rcut - m->rmin);
   a.sb = -(m->rmin + m->rcut) / (m->rcut - m->rmin);
   a.rcut = m->rcut;
@@ -588,9 +589,11 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
   SysArgs a = make_sys_args(m, sys, use);
   if (m->nsp > 1 && use.n_pairs > 0) {
     // neighbour species per pair, for the per-species passes of the adjoint pair kernel
-    if ((rc = m->zpair.reserve((size_t)use.n_pairs))) return rc;
-    launch_pair_species(use.j, sys->species, m->nsp, use.n_pairs, (unsigned char*)m->zpair.p, s);
-    a.zpair = (const unsigned char*)m->zpair.p;
+    if ((rc = m->plink.reserve((size_t)use.n_pairs * 4)) || (rc = m->pfirst.reserve((size_t)n * m->nsp * 4)))
+      return rc;
+    launch_pair_links(use.off, use.j, sys->species, m->nsp, n, (int*)m->plink.p, (int*)m->pfirst.p, s);
+    a.plink = (const int*)m->plink.p;
+    a.pfirst = (const int*)m->pfirst.p;
   }
   double *mom = (double*)m->mom.p, *cbar = (double*)m->cbar.p, *mbar = (double*)m->mbar.p;
   double *mdot = (double*)m->mdot.p, *cbard = (double*)m->cbard.p, *mbard = (double*)m->mbard.p;

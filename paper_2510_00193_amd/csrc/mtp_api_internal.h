@@ -58,7 +58,7 @@ struct mtp_model {
   DevBuf nl_off, nl_j, nl_shift, nl_rev;               // internally built neighbour list
   DevBuf mom, cbar, mbar, bvals, g, fown, eatom, wpart;  // per-chunk / per-pair workspace
   DevBuf mdot, cbard, mbard, xout, dxi_part, cpart;   // parameter-adjoint workspace
-  DevBuf zpair;                                         // neighbour species per pair (adjoint)
+  DevBuf plink, pfirst;                                 // per-species pair chains (adjoint)
   DevBuf scratch;
   long wblocks = 0;
   mtp::NbrWork* nbr = nullptr;

@@ -37,7 +37,7 @@ struct mtp_batch {
   const double* pos = nullptr;
   const int* species = nullptr;
   DevBuf atom_off, cfg, cells, cinv, reach, off, nj, shift, rev, perm;
-  DevBuf zpair;                    // neighbour species per pair (fixed with the lists)
+  DevBuf plink, pfirst;            // per-species pair chains (fixed with the lists)
   std::vector<int> h_off;          // host copy of the CSR offsets (neighbour counts)
   // workspace
   DevBuf eatom, watom, g, fown, forces, energy, virial, mom, cbar, mbar, mdot, cbard, mbard, xout, dxi_part,
@@ -142,7 +142,8 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
   a.cfg = (const int*)b->cfg.p;
   a.perm = (const int*)b->perm.p;
   a.ebar = nullptr;
-  a.zpair = b->zpair.p ? (const unsigned char*)b->zpair.p : nullptr;
+  a.plink = b->plink.p ? (const int*)b->plink.p : nullptr;
+  a.pfirst = b->pfirst.p ? (const int*)b->pfirst.p : nullptr;
   a.sa = 2.0 / (m->rcut - m->rmin);
   a.sb = -(m->rmin + m->rcut) / (m->rcut - m->rmin);
   a.rcut = m->rcut;
@@ -319,11 +320,11 @@ int mtp_batch_create(mtp_model* m, int n_cfg, const int* atom_off, const double*
   }
   b->npairs = total;
   if (m->nsp > 1 && total > 0) {
-    if ((rc = b->zpair.reserve((size_t)total))) {
+    if ((rc = b->plink.reserve((size_t)total * 4)) || (rc = b->pfirst.reserve((size_t)n * m->nsp * 4))) {
       delete b;
-      return mtp_fail(rc, "allocating the pair species failed");
+      return mtp_fail(rc, "allocating the pair species chains failed");
     }
-    launch_pair_species(nj, species, m->nsp, total, (unsigned char*)b->zpair.p, s);
+    launch_pair_links((const int*)b->off.p, nj, species, m->nsp, (int)n, (int*)b->plink.p, (int*)b->pfirst.p, s);
   }
   b->h_off.resize(n + 1);
   if (hipMemcpy(b->h_off.data(), b->off.p, (n + 1) * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {

@@ -168,19 +168,40 @@ __global__ __launch_bounds__(kNT) void k_species_grad_cfg(const int* __restrict_
   if (threadIdx.x == 0) out[t] = v;
 }
 
-__global__ void k_pair_species(const int* __restrict__ nj, const int* __restrict__ species, int nsp,
-                               long long npairs, unsigned char* __restrict__ zp) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < npairs) zp[p] = (unsigned char)clamp_species(species[nj[p]], nsp);
+// Per-species chains through each CSR row: pfirst[i][t] is the first pair of atom i whose
+// neighbour has species t and plink[p] the next pair of the same row and neighbour species
+// (-1 ends a chain). One lane per atom walks its row backwards.
+__global__ void k_pair_links(const int* __restrict__ off, const int* __restrict__ nj,
+                             const int* __restrict__ species, int nsp, int n, int* __restrict__ plink,
+                             int* __restrict__ pfirst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int last[kMaxSpecies];
+#pragma unroll
+  for (int t = 0; t < kMaxSpecies; ++t) last[t] = -1;
+  for (int q = off[i + 1] - 1; q >= off[i]; --q) {
+    const int z = clamp_species(species[nj[q]], nsp);
+    int nxt = -1;
+#pragma unroll
+    for (int t = 0; t < kMaxSpecies; ++t)
+      if (t == z) {
+        nxt = last[t];
+        last[t] = q;
+      }
+    plink[q] = nxt;
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxSpecies; ++t)
+    if (t < nsp) pfirst[(long)i * nsp + t] = last[t];
 }
 
 }  // namespace
 
-void launch_pair_species(const int* nj, const int* species, int nsp, long long npairs, unsigned char* zp,
-                         hipStream_t s) {
-  if (npairs <= 0) return;
-  hipLaunchKernelGGL(k_pair_species, dim3((unsigned)((npairs + kNT - 1) / kNT)), dim3(kNT), 0, s, nj, species, nsp,
-                     npairs, zp);
+void launch_pair_links(const int* off, const int* nj, const int* species, int nsp, int n, int* plink,
+                       int* pfirst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pair_links, dim3((n + kNT - 1) / kNT), dim3(kNT), 0, s, off, nj, species, nsp, n, plink,
+                     pfirst);
 }
 
 void launch_segsum(const double* x, long stride, const int* seg_off, int nseg, int ncomp, double* out,

@@ -23,7 +23,9 @@ struct SysArgs {
   const int* cfg;         // [N] configuration of each atom (batches), or null
   const int* perm;        // [N] processing order: lane k of the sweep takes atom perm[k], or null
   const double* ebar;     // [n_cfg] per-configuration energy cotangent (batches), or null
-  const unsigned char* zpair;  // [P] species of each pair's neighbour (clamped), or null
+  // per-species chains through the rows (launch_pair_links), or null for one species
+  const int* plink;       // [P] next pair of the same row and neighbour species, -1 at the end
+  const int* pfirst;      // [N][nsp] first pair of each neighbour species, -1 if none
   double sa, sb, rcut;    // u = sa r + sb
   int nsp, nmu, ncheb;
 };
@@ -125,8 +127,8 @@ void launch_grade(const double* B, long ld, int n, const double* ainv, int na, i
                   double* grade, hipStream_t s);
 void launch_max(const double* x, long n, double* out, hipStream_t s);
 // zp[p] = species of neighbour nj[p], clamped to [0, nsp)
-void launch_pair_species(const int* nj, const int* species, int nsp, long long npairs, unsigned char* zp,
-                         hipStream_t s);
+void launch_pair_links(const int* off, const int* nj, const int* species, int nsp, int n, int* plink,
+                       int* pfirst, hipStream_t s);
 // out[0] = max_k |(b . ainv)_k| for one descriptor b [na]
 void launch_cfg_grade(const double* b, const double* ainv, int na, double* out, hipStream_t s);
 

@@ -398,8 +398,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Radial-coefficient gradient: per pair (i, j) with species (s, t),
 //   dc[s][t][mu][b] += Q_b (ebar S_mu - A_mu) - Q'_b (rhat . delta) S_mu,
-// accumulated per lane for one neighbour species at a time and summed over the wave with a
-// fixed butterfly; one partial per (workgroup, s, t) lands in cpart. G is an adjoint group: a
+// accumulated per lane for one neighbour species at a time (following the per-species pair
+// chains) and summed over the wave with a fixed butterfly; one partial per (workgroup, s, t)
+// lands in cpart. G is an adjoint group: a
 // moment range small enough that its adjoints, their tangents and the sums of its mu values
 // [AMU_LO, AMU_HI] stay in registers; the partial rows of the other mu values are written as
 // zeros. NC is the compile-time Chebyshev count (0: runtime count up to kMaxCheb); every index
@@ -431,24 +432,24 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
   const double fix = fbar[3 * i], fiy = fbar[3 * i + 1], fiz = fbar[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
   const int p0 = live ? a.off[i] : 0, p1 = live ? a.off[i + 1] : 0;
-  // species of the neighbour of pair p (precomputed bytes when available)
-  auto zj_of = [&](int p) -> int {
-    return a.zpair ? (int)a.zpair[p] : clamp_species(a.species[a.nj[p]], a.nsp);
-  };
   for (int t = 0; t < a.nsp; ++t) {
     double acc[NM * NQ];
 #pragma unroll
     for (int k = 0; k < NM * NQ; ++k) acc[k] = 0.0;
-    // each lane steps to its own next pair of species t, so the wave runs the pair body
-    // max over lanes (not the row length) times per species
-    int p = p0;
+    // each lane follows its row's chain of species-t pairs (the whole row with one species),
+    // so the wave runs the pair body max over lanes (not the row length) times per species;
+    // the next link and the next pair's list entries are loaded one pair ahead
+    auto link = [&](int q) -> int { return a.plink ? a.plink[q] : (q + 1 < p1 ? q + 1 : -1); };
+    int p = !live ? -1 : a.pfirst ? a.pfirst[(long)i * a.nsp + t] : (p0 < p1 ? p0 : -1);
+    int pn = p >= 0 ? link(p) : -1;
+    int j = p >= 0 ? a.nj[p] : 0, sh = p >= 0 ? a.shift[p] : 0;
     for (;;) {
-      while (p < p1 && zj_of(p) != t) ++p;
-      if (!__any(p < p1)) break;
-      if (p >= p1) continue;
-      const int j = a.nj[p];
+      if (!__any(p >= 0)) break;
+      if (p < 0) continue;
+      const int pnn = pn >= 0 ? link(pn) : -1;
+      const int jn = pn >= 0 ? a.nj[pn] : 0, shn = pn >= 0 ? a.shift[pn] : 0;
       int n1, n2, n3;
-      unpack_shift(a.shift[p], n1, n2, n3);
+      unpack_shift(sh, n1, n2, n3);
       double dx, dy, dz;
       pair_displacement(rix, riy, riz, a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2], n1, n2,
                         n3, H, dx, dy, dz);
@@ -490,7 +491,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 #pragma unroll
         for (int k = 0; k < NM; ++k) acc[k * NQ + bq] = fma(q, X[k], fma(qp, Y[k], acc[k * NQ + bq]));
       }
-      ++p;
+      p = pn;
+      pn = pnn;
+      j = jn;
+      sh = shn;
     }
     for (int sp = 0; sp < a.nsp; ++sp) {
       double* dst = cpart + (long)b * a.nsp * a.nsp * NMU * nq + (long)(sp * a.nsp + t) * NMU * nq;

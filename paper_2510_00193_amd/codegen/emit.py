@@ -511,6 +511,11 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     w("static constexpr int AGROUP_HI[NAGROUP] = {" + ", ".join(str(g[1]) for g in agroups) + "};")
     w("static constexpr int AMU_LO[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[0]][0]) for g in agroups) + "};")
     w("static constexpr int AMU_HI[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[1] - 1][0]) for g in agroups) + "};")
+    # ranges of the moment-tangent kernel
+    tgroups = tangent_moment_groups(groups, agroups)
+    w(f"static constexpr int NTGROUP = {len(tgroups)};")
+    w("static constexpr int TGROUP_LO[NTGROUP] = {" + ", ".join(str(g[0]) for g in tgroups) + "};")
+    w("static constexpr int TGROUP_HI[NTGROUP] = {" + ", ".join(str(g[1]) for g in tgroups) + "};")
     w("// flat moment layout: (mu, a, b, c) of component e")
     w("static constexpr int ENTRIES[NMOM][4] = {" + ", ".join("{%d, %d, %d, %d}" % it for it in prog.layout.items) + "};")
     # a! b! c! of each entry: pair_grad takes the moment adjoints scaled by it
@@ -856,7 +861,7 @@ def _emit_products_tangent(w: _W, prog: Program):
     w("}")
 
 
-def _emit_tangent_dispatchers(w: _W, n_groups: int, n_agroups: int):
+def _emit_tangent_dispatchers(w: _W, n_groups: int, n_agroups: int, n_tgroups: int):
     sigs = (
         ("tan_moments", "R* __restrict__ md, const R* __restrict__ f, const R* __restrict__ fp, R x, R y, R z, "
                         "R ex, R ey, R ez, R rdot", "md, f, fp, x, y, z, ex, ey, ez, rdot", "class R", "<R>"),
@@ -869,17 +874,26 @@ def _emit_tangent_dispatchers(w: _W, n_groups: int, n_agroups: int):
         w(f"template <int G, {tparams}>")
         w(f"static __device__ __forceinline__ void {name}({params}) {{")
         w.push()
-        for g in range(n_agroups if name == "adj_pair" else n_groups):
+        count = {"adj_pair": n_agroups, "tan_moments": n_tgroups}.get(name, n_groups)
+        for g in range(count):
             kw = "if constexpr" if g == 0 else "else if constexpr"
             w(f"{kw} (G == {g}) {name}_g{g}{targs}({args});")
         w.pop()
         w("}")
 
 
+def tangent_moment_groups(groups, agroups):
+    """Ranges of the moment-tangent kernel: the adjoint ranges where the chain has one group
+    (its whole layout does not fit in registers next to the tangent monomials), else the
+    chain's groups (measured faster at level 20 than seven passes over the pairs)."""
+    return agroups if len(groups) == 1 else groups
+
+
 def emit_tangent_parts(w: _W, prog: Program, groups, agroups):
-    _emit_tangent_pair_functions(w, prog, groups)
+    tgroups = tangent_moment_groups(groups, agroups)
+    _emit_tangent_pair_functions(w, prog, tgroups)
     _emit_adj_pair_functions(w, prog, agroups)
     _emit_components_forward_tangent(w, prog)
     _emit_components_reverse_tangent(w, prog, groups)
     _emit_products_tangent(w, prog)
-    _emit_tangent_dispatchers(w, len(groups), len(agroups))
+    _emit_tangent_dispatchers(w, len(groups), len(agroups), len(tgroups))

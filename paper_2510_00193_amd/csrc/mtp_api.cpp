@@ -616,7 +616,7 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
       ProfScope ps(&m->prof, P_PROG_REV, s);
       L.chain[0].prog_rev(g, mom, ld, cn, cbar, mbar, s);
     }
-    for (int g = 0; g < L.ngroup; ++g) {
+    for (int g = 0; g < L.adj.ntgroup; ++g) {
       ProfScope ps(&m->prof, P_TANGENT, s);
       L.adj.tan_moments(g, a, fbar, i0, cn, mdot, ld, s);
     }

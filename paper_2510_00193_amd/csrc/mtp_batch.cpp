@@ -223,7 +223,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
       ProfScope ps(&m->prof, P_PROG_REV, s);
       K.prog_rev(gi, b->mom.p, ld, cn, b->cbar.p, b->mbar.p, s);
     }
-    for (int gi = 0; gi < L.ngroup; ++gi) {
+    for (int gi = 0; gi < L.adj.ntgroup; ++gi) {
       ProfScope ps(&m->prof, P_TANGENT, s);
       L.adj.tan_moments(gi, a, fbar, (int)i0, cn, (double*)b->mdot.p, ld, s);
     }

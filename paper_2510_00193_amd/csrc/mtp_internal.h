@@ -61,6 +61,7 @@ struct AdjOps {
   void (*adj_pairs)(int grp, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                     const double* mbd, long ld, double ebar, double* cpart, hipStream_t s);
   int nagroup;
+  int ntgroup;  // moment ranges of tan_moments (the adjoint ranges or the chain's groups)
 };
 
 // Launchers of one compiled level (assembled from the level's translation units).

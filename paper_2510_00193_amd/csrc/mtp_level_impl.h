@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
   const int i = atom_at(a, i0 + li);
   double H[9];
   load_cell(a, i, H);
-  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
+  constexpr int LO = L::TGROUP_LO[G], HI = L::TGROUP_HI[G], NG = HI - LO;
   double md[NG];
 #pragma unroll
   for (int e = 0; e < NG; ++e) md[e] = 0.0;
@@ -615,7 +615,7 @@ struct AdjImpl {
   }
   static void tan_moments(int g, const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
                           hipStream_t s) {
-    tan_moments_d(g, a, fbar, i0, n, md, ld, s, std::make_index_sequence<L::NGROUP>{});
+    tan_moments_d(g, a, fbar, i0, n, md, ld, s, std::make_index_sequence<L::NTGROUP>{});
   }
   static void tan_forward(const SysArgs& a, const double* m, const double* md, long ld, int i0, int n,
                           const double* xi, double ebar, double* out, double* cbard, hipStream_t s) {
@@ -658,6 +658,7 @@ struct AdjImpl {
     o.tan_moments = &tan_moments;
     o.adj_pairs = &adj_pairs;
     o.nagroup = L::NAGROUP;
+    o.ntgroup = L::NTGROUP;
     return o;
   }
 };

@@ -62,9 +62,9 @@ static void moments_of(const std::vector<double>& d, std::vector<double>& m) {
 }
 
 template <int G>
-static void tan_group(const std::vector<double>& d, const std::vector<double>& dl, std::vector<double>& md) {
+static void tan_range(const std::vector<double>& d, const std::vector<double>& dl, std::vector<double>& md) {
   const int np = (int)d.size() / 3;
-  const int lo = L::GROUP_LO[G];
+  const int lo = L::TGROUP_LO[G];
   for (int p = 0; p < np; ++p) {
     double x = d[3 * p], y = d[3 * p + 1], z = d[3 * p + 2];
     double r = std::sqrt(x * x + y * y + z * z), f[L::NMU], fp[L::NMU];
@@ -72,7 +72,16 @@ static void tan_group(const std::vector<double>& d, const std::vector<double>& d
     const double rdot = (x * dl[3 * p] + y * dl[3 * p + 1] + z * dl[3 * p + 2]) / r;
     double part[L::NMOM] = {0};
     L::tan_moments<G>(part, f, fp, x, y, z, dl[3 * p], dl[3 * p + 1], dl[3 * p + 2], rdot);
-    for (int e = lo; e < L::GROUP_HI[G]; ++e) md[e] += part[e - lo];
+    for (int e = lo; e < L::TGROUP_HI[G]; ++e) md[e] += part[e - lo];
+  }
+}
+
+// tangent of the moments over every moment-tangent range of the level
+template <int G>
+static void tan_group(const std::vector<double>& d, const std::vector<double>& dl, std::vector<double>& md) {
+  if constexpr (G < L::NTGROUP) {
+    tan_range<G>(d, dl, md);
+    tan_group<G + 1>(d, dl, md);
   }
 }
 
@@ -107,12 +116,6 @@ int main() {
     moments_of(dm, mm);
     for (int e = 0; e < L::NMOM; ++e) fd[e] = (mp[e] - mm[e]) / (2 * h);
     tan_group<0>(d, dl, md);
-#if MTP_NGROUP > 1
-    tan_group<1>(d, dl, md);
-#endif
-#if MTP_NGROUP > 2
-    tan_group<2>(d, dl, md);
-#endif
     std::printf("tan_moments %.3e\n", relerr(md, fd));
   }
   // ---- forward tangent of the contractions

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="no host compiler")
-@pytest.mark.parametrize("level,groups", [(6, 1), (10, 1), (10, 2), (12, 3), (14, 2)])
+@pytest.mark.parametrize("level,groups", [(6, 1), (10, 1), (10, 2), (12, 3), (14, 1), (14, 2)])
 def test_generated_tangents_match_differences(tmp_path, level, groups):
     hdr = tmp_path / f"L{level}.inc"
     hdr.write_text(emit_level(level, groups))

@@ -71,3 +71,10 @@ def test_vjp_level14_runtime_chebyshev_count():
     s, p = small_lattice(904, (3, 3, 3), 3.16, 0.08, 14, 2, n_cheb=6)
     rng = np.random.default_rng(4)
     _compare(p, s, 1.3, rng.normal(size=(s.n_atoms, 3)), "L14-ncheb6")
+
+
+def test_vjp_single_species_walks_whole_rows():
+    """One species: no per-species chains are built and the pair kernel walks each row."""
+    s, p = small_lattice(905, (3, 3, 3), 3.16, 0.08, 12, 1)
+    rng = np.random.default_rng(5)
+    _compare(p, s, -0.6, rng.normal(size=(s.n_atoms, 3)), "L12-one-species")

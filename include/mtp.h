@@ -98,6 +98,13 @@ typedef struct {
   const int* shift;      /* [n_pairs] */
   const int* rev;        /* [n_pairs] */
   long long n_pairs;
+  int checked;           /* 1: written by mtp_neighbors for these positions and cell and not
+                            modified since, used as is.  0: validated before use (one pass over
+                            the list on the device and one synchronization): off[0] = 0,
+                            off[N] = n_pairs, rows non-decreasing, 0 <= j < N, every rev[p] a pair
+                            of row j[p] whose partner is the row's atom, with the negated shift,
+                            and rev[rev[p]] = p; species in [0, n_species).  A list that fails
+                            returns MTP_ERR_ARG and nothing else is enqueued. */
 } mtp_nlist;
 
 /* Number of compiled levels and their values (host array of at least 32 ints). */
@@ -123,17 +130,21 @@ int mtp_sizes(const mtp_model* m, int* n_alpha, int* n_mu, int* n_moments, int* 
 int mtp_set_params(mtp_model* m, const double* radial, const double* linear, const double* shift,
                    int on_device, void* stream);
 
-/* Build the canonical neighbour list of a system into caller buffers (device).
+/* Build the canonical neighbour list of a system into caller buffers (device).  The paper's
+ * variants read LAMMPS half lists (the Kokkos flags of Section 2.3, newton on, neigh half); this
+ * library builds a full list itself so that every row is complete and the result is
+ * reproducible bit for bit.
  * off must hold N + 1 ints; j, shift and rev must hold cap ints each (rev may be NULL).
  * *n_pairs (host) receives the pair count.  If it exceeds cap, nothing but off is written
  * and MTP_ERR_CAPACITY is returned.  Synchronizes the stream once (to read the count). */
 int mtp_neighbors(mtp_model* m, const mtp_system* sys, int* off, int* j, int* shift, int* rev,
                   long long cap, long long* n_pairs, void* stream);
 
-/* Energy, forces and virial (device outputs; any may be NULL):
+/* Energy, forces and virial (device outputs; any may be NULL), the inference use case of
+ * Section 2.1 (energies, forces and stresses):
  *   energy [1], e_atom [N], forces [N][3], virial [6] as xx, yy, zz, xy, xz, yz with
  *   W_ab = -sum_pairs d_a g_b (g = dE_i/dd_ij), positive under repulsion.
- * nl: a list from mtp_neighbors for these positions, or NULL to build one internally
+ * nl: a list for these positions (see mtp_nlist.checked), or NULL to build one internally
  * (then the call synchronizes once).  Results are deterministic run to run. */
 int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double* energy,
                 double* e_atom, double* forces, double* virial, void* stream);
@@ -154,7 +165,9 @@ int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const do
 int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
                      double* descriptor, double* grade, void* stream);
 
-/* Vector-Jacobian product of (E, F) with respect to the coefficients:
+/* Vector-Jacobian product of (E, F) with respect to the coefficients.  The paper keeps MLIP-3's
+ * potential files and its fitting (Section 1 and Section 2.3); this call is the gradient a fit
+ * needs, computed on the device:
  *   d_linear [n_alpha], d_radial [n_species^2 n_mu n_cheb], d_shift [n_species] (device) =
  *   ebar dE/dtheta + sum_k fbar_k . dF_k/dtheta,  fbar device [N][3].
  * For the loss (E - E0)^2 + sum |F - F0|^2 pass ebar = 2 (E - E0), fbar = 2 (F - F0). */
@@ -193,6 +206,13 @@ int mtp_batch_run(mtp_batch* b, const double* e_target, const double* f_target, 
                   double* forces, double* virial, double* loss, double* d_linear, double* d_radial,
                   double* d_shift, int use_graph, void* stream);
 int mtp_batch_tune(mtp_batch* b, const char* cache_path, int* choice, void* stream);
+/* mtp_batch_vjp: the vector-Jacobian product of every configuration's (E_c, F) for any
+ *   cotangents: d_linear [n_alpha], d_radial [n_sp^2 n_mu n_cheb], d_shift [n_sp] (device) =
+ *   sum_c ebar_c dE_c/dtheta + sum_i fbar_i . dF_i/dtheta, with ebar device [n_cfg] and fbar
+ *   device [N][3].  The forward state is recomputed (nothing is kept from an earlier run).
+ *   Allocates nothing, never synchronizes; use_graph as for mtp_batch_run. */
+int mtp_batch_vjp(mtp_batch* b, const double* ebar, const double* fbar, double* d_linear, double* d_radial,
+                  double* d_shift, int use_graph, void* stream);
 int mtp_batch_schedule(mtp_batch* b, int sorted, int chunk_atoms);
 int mtp_batch_sizes(const mtp_batch* b, int* n_atoms, long long* n_pairs, int* sorted, int* chunk_atoms);
 int mtp_batch_neighbors(const mtp_batch* b, const int** off, const int** j, const int** shift,

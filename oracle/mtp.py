@@ -221,13 +221,6 @@ def param_vjp(model, struct, ebar, fbar, nl=None):
     return tuple(g.detach().numpy() for g in grads)
 
 
-def loss(model, struct, e0, f0, nl=None, radial=None, linear=None, shift=None):
-    """Configuration loss (E - E0)^2 + sum_k |F_k - F0_k|^2 (unit weights)."""
-    out = energy_forces_virial(model, struct, nl, radial, linear, shift, create_graph=True)
-    f0_t = torch.as_tensor(np.asarray(f0, dtype=np.float64))
-    return (out["E"] - float(e0)) ** 2 + ((out["F"] - f0_t) ** 2).sum()
-
-
 # ----------------------------------------------------------------------------- sampled atoms
 
 

@@ -6,3 +6,4 @@ in hand-written HIP kernels behind the C ABI declared in include/mtp.h.
 This package only builds the library and marshals arguments to it.
 """
 from .api import Batch, NeighborList, Potential, compiled_levels, level_info  # noqa: F401
+from .autograd import MTPBatchFunction, MTPFunction, batch_energy_forces, energy_forces  # noqa: F401

@@ -23,7 +23,7 @@ MTP_FP32_MOMENTS = 1
 MTP_GRADE_FP64 = 0
 MTP_GRADE_FP32SPLIT = 1
 
-EXPORTS = ("mtp_batch_create", "mtp_batch_run", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
+EXPORTS = ("mtp_batch_create", "mtp_batch_run", "mtp_batch_vjp", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
            "mtp_batch_neighbors", "mtp_batch_destroy", "mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset", "mtp_create", "mtp_destroy", "mtp_last_error", "mtp_sizes", "mtp_set_params",
            "mtp_neighbors", "mtp_compute", "mtp_grade", "mtp_grade_config", "mtp_param_grad")
 
@@ -63,6 +63,7 @@ class MtpNlist(ctypes.Structure):
         ("shift", ctypes.c_void_p),
         ("rev", ctypes.c_void_p),
         ("n_pairs", ctypes.c_longlong),
+        ("checked", ctypes.c_int),
     ]
 
 
@@ -111,6 +112,7 @@ def open_library(path: str):
                                        vp, vp]
     lib.mtp_batch_create.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, c_double_p, ctypes.POINTER(vp), vp]
     lib.mtp_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp]
+    lib.mtp_batch_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i, vp]
     lib.mtp_batch_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i), vp]
     lib.mtp_batch_schedule.argtypes = [vp, i, i]
     lib.mtp_batch_sizes.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(ll), ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -118,7 +120,7 @@ def open_library(path: str):
                                         ctypes.POINTER(vp)]
     lib.mtp_batch_destroy.argtypes = [vp]
     lib.mtp_batch_destroy.restype = None
-    for name in ("mtp_batch_create", "mtp_batch_run", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
+    for name in ("mtp_batch_create", "mtp_batch_run", "mtp_batch_vjp", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
                  "mtp_batch_neighbors"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset",

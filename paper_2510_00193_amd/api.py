@@ -39,21 +39,29 @@ def _dev(t, dtype, shape=None, name=""):
 
 @dataclass
 class NeighborList:
-    """Canonical CSR list (device int32 tensors)."""
+    """Canonical CSR list (device int32 tensors).
+
+    checked is True for a list returned by Potential.neighbors (the library uses it as is); a
+    list assembled by the caller keeps the default False and is validated by the library on
+    every use (one pass over the list and one synchronization).
+    """
 
     off: torch.Tensor
     j: torch.Tensor
     shift: torch.Tensor
     rev: torch.Tensor
+    checked: bool = False
 
     @property
     def n_pairs(self) -> int:
         return int(self.j.shape[0])
 
     def _c(self):
+        for name in ("off", "j", "shift", "rev"):
+            _dev(getattr(self, name), torch.int32, name=name)
         return MtpNlist(self.off.data_ptr(), self.j.data_ptr() if self.n_pairs else None,
                         self.shift.data_ptr() if self.n_pairs else None,
-                        self.rev.data_ptr() if self.n_pairs else None, self.n_pairs)
+                        self.rev.data_ptr() if self.n_pairs else None, self.n_pairs, 1 if self.checked else 0)
 
 
 def compiled_levels():
@@ -168,7 +176,7 @@ class Potential:
         check(self._lib.mtp_neighbors(self._h, ctypes.byref(sysc), _ptr(off), _ptr(j), _ptr(sh), _ptr(rev),
                                       int(cap), ctypes.byref(total), _stream()))
         p = total.value
-        return NeighborList(off, j[:p], sh[:p], rev[:p])
+        return NeighborList(off, j[:p], sh[:p], rev[:p], checked=True)
 
     def compute(self, pos, species, cell, nlist=None, forces=True, virial=True, e_atom=False):
         sysc, n = self._system(pos, species, cell)
@@ -282,6 +290,23 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         check(self._lib.mtp_batch_tune(self._h, path, choice, _stream()))
         return {"sorted": choice[0], "chunk_atoms": choice[1]}
+
+    def vjp(self, ebar, fbar, use_graph=False):
+        """sum_c ebar_c dE_c/dtheta + sum_i fbar_i . dF_i/dtheta for device cotangents ebar [n_cfg]
+        and fbar [N, 3]: (d_linear, d_radial, d_shift) as new device tensors."""
+        _dev(ebar, torch.float64, (self.n_cfg,), "ebar")
+        _dev(fbar, torch.float64, (self.n_atoms, 3), "fbar")
+        p = self._pot
+        dev = self.pos.device
+        if getattr(self, "_vjp_out", None) is None or not use_graph:
+            self._vjp_out = (torch.empty(p.n_alpha, dtype=torch.float64, device=dev),
+                             torch.empty((p.n_species, p.n_species, p.n_mu, p.n_cheb), dtype=torch.float64,
+                                         device=dev),
+                             torch.empty(p.n_species, dtype=torch.float64, device=dev))
+        dl, dr, ds = self._vjp_out
+        check(self._lib.mtp_batch_vjp(self._h, _ptr(ebar), _ptr(fbar), _ptr(dl), _ptr(dr), _ptr(ds),
+                                      1 if use_graph else 0, _stream()))
+        return (dl.clone(), dr.clone(), ds.clone()) if use_graph else (dl, dr, ds)
 
     def neighbors(self):
         ptrs = [ctypes.c_void_p() for _ in range(4)]

@@ -316,6 +316,24 @@ int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_
   if (nl) {
     if (!nl->off || (nl->n_pairs > 0 && (!nl->j || !nl->shift || !nl->rev)) || nl->n_pairs < 0)
       return mtp_fail(MTP_ERR_ARG, "incomplete neighbour list");
+    if (nl->n_pairs >= (1LL << 31)) return mtp_fail(MTP_ERR_ARG, "more than 2^31 - 1 pairs");
+    if (!nl->checked) {
+      if (sys->n_atoms == 0 && nl->n_pairs != 0) return mtp_fail(MTP_ERR_ARG, "pairs in an empty system");
+      if (sys->n_atoms > 0) {
+        int rc = m->flag.reserve(sizeof(int));
+        if (rc) return rc;
+        int bad = 0;
+        HIP_TRY(hipMemsetAsync(m->flag.p, 0, sizeof(int), s));
+        launch_check_nlist(nl->off, nl->j, nl->shift, nl->rev, sys->species, sys->n_atoms, nl->n_pairs, m->nsp,
+                           (int*)m->flag.p, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&bad, m->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad)
+          return mtp_fail(MTP_ERR_ARG, "inconsistent neighbour list (offsets, partner index, mirror or shift) "
+                                       "or species outside [0, n_species)");
+      }
+    }
     *out = *nl;
     return MTP_OK;
   }
@@ -327,6 +345,7 @@ int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_
   out->shift = (const int*)m->nl_shift.p;
   out->rev = (const int*)m->nl_rev.p;
   out->n_pairs = total;
+  out->checked = 1;
   return MTP_OK;
 }
 

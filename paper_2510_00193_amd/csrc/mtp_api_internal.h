@@ -60,6 +60,7 @@ struct mtp_model {
   DevBuf mdot, cbard, mbard, xout, dxi_part, cpart;   // parameter-adjoint workspace
   DevBuf plink, pfirst;                                 // per-species pair chains (adjoint)
   DevBuf scratch;
+  DevBuf flag;                                          // status word of the list check
   long wblocks = 0;
   mtp::NbrWork* nbr = nullptr;
   Profiler prof;

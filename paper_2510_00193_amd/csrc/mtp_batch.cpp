@@ -122,9 +122,11 @@ static int set_schedule(mtp_batch* b, int sorted, int chunk) {
 }
 
 // The kernel sequence of one batch run (no allocation, no synchronization, no memset).
-static void run_impl(mtp_batch* b, const double* e_target, const double* f_target, double* energy,
-                     double* forces, double* virial, double* loss, double* d_linear, double* d_radial,
-                     double* d_shift, hipStream_t s) {
+// With cotangents (ebar_in [n_cfg], fbar_in [N][3]) the adjoint runs on them instead of the loss
+// cotangents of targets.
+static void run_impl(mtp_batch* b, const double* e_target, const double* f_target, const double* ebar_in,
+                     const double* fbar_in, double* energy, double* forces, double* virial, double* loss,
+                     double* d_linear, double* d_radial, double* d_shift, hipStream_t s) {
   mtp_model* m = b->m;
   const LevelOps& L = m->ops;
   const ChainOps& K = L.chain[2];
@@ -188,15 +190,20 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     launch_segsum(ea, 1, (const int*)b->atom_off.p, b->ncfg, 1, E, 1, s);
     launch_segsum(wa, 6, (const int*)b->atom_off.p, b->ncfg, 6, virial ? virial : (double*)b->virial.p, 6, s);
   }
-  if (!e_target || !f_target) return;
-  // ---- loss cotangents on the device
-  double* ebar = (double*)b->ebar_cfg.p;
-  double* fbar = (double*)b->fbar.p;
-  double* parts = (double*)b->parts.p;
-  {
+  const bool vjp = ebar_in && fbar_in;
+  if (!vjp && (!e_target || !f_target)) return;
+  const double* ebar = ebar_in;
+  const double* fbar = fbar_in;
+  if (!vjp) {
+    // ---- loss cotangents on the device
+    double* eb = (double*)b->ebar_cfg.p;
+    double* fb = (double*)b->fbar.p;
+    double* parts = (double*)b->parts.p;
     ProfScope ps(&m->prof, P_REDUCE, s);
-    launch_loss(E, e_target, b->ncfg, F, f_target, n, ebar, fbar, parts, parts + b->ncfg, s);
+    launch_loss(E, e_target, b->ncfg, F, f_target, n, eb, fb, parts, parts + b->ncfg, s);
     if (loss) launch_sum(parts, (long)b->ncfg + n, 1, loss, s);
+    ebar = eb;
+    fbar = fb;
   }
   // ---- adjoint
   a.ebar = ebar;
@@ -251,6 +258,10 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
   launch_rowsum(cpart, 1, KR, part, (int)KR, d_radial, 1, s);
   launch_species_grad_cfg(b->species, (const int*)b->cfg.p, ebar, n, m->nsp, d_shift, s);
 }
+
+static int launch_run(mtp_batch* b, const double* e_target, const double* f_target, const double* ebar,
+                      const double* fbar, double* energy, double* forces, double* virial, double* loss,
+                      double* d_linear, double* d_radial, double* d_shift, int use_graph, hipStream_t s);
 
 extern "C" {
 
@@ -372,13 +383,33 @@ int mtp_batch_run(mtp_batch* b, const double* e_target, const double* f_target, 
   if (adj && (!e_target || !f_target || !d_linear || !d_radial || !d_shift))
     return mtp_fail(MTP_ERR_ARG, "the loss gradient needs both targets and all three gradient outputs");
   if (b->n == 0) return mtp_fail(MTP_ERR_ARG, "empty batch");
-  hipStream_t s = (hipStream_t)stream;
+  return launch_run(b, e_target, f_target, nullptr, nullptr, energy, forces, virial, loss, d_linear, d_radial,
+                    d_shift, use_graph, (hipStream_t)stream);
+}
+
+int mtp_batch_vjp(mtp_batch* b, const double* ebar, const double* fbar, double* d_linear, double* d_radial,
+                  double* d_shift, int use_graph, void* stream) {
+  if (!b) return mtp_fail(MTP_ERR_ARG, "null batch");
+  if (!ebar || !fbar || !d_linear || !d_radial || !d_shift)
+    return mtp_fail(MTP_ERR_ARG, "the product needs both cotangents and all three gradient outputs");
+  if (b->n == 0) return mtp_fail(MTP_ERR_ARG, "empty batch");
+  return launch_run(b, nullptr, nullptr, ebar, fbar, nullptr, nullptr, nullptr, nullptr, d_linear, d_radial,
+                    d_shift, use_graph, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// Enqueue run_impl directly, or as the replay of a graph captured once per set of pointers.
+static int launch_run(mtp_batch* b, const double* e_target, const double* f_target, const double* ebar,
+                      const double* fbar, double* energy, double* forces, double* virial, double* loss,
+                      double* d_linear, double* d_radial, double* d_shift, int use_graph, hipStream_t s) {
   if (!use_graph) {
-    run_impl(b, e_target, f_target, energy, forces, virial, loss, d_linear, d_radial, d_shift, s);
+    run_impl(b, e_target, f_target, ebar, fbar, energy, forces, virial, loss, d_linear, d_radial, d_shift, s);
     HIP_TRY(hipGetLastError());
     return MTP_OK;
   }
-  std::vector<const void*> key = {e_target, f_target, energy, forces, virial, loss, d_linear, d_radial, d_shift};
+  std::vector<const void*> key = {e_target, f_target, ebar, fbar, energy, forces, virial, loss, d_linear, d_radial,
+                                  d_shift};
   if (!b->gs) {
     HIP_TRY(hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
@@ -392,7 +423,7 @@ int mtp_batch_run(mtp_batch* b, const double* e_target, const double* f_target, 
     const bool prof = b->m->prof.on;
     b->m->prof.on = false;  // no event records inside the graph
     HIP_TRY(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
-    run_impl(b, e_target, f_target, energy, forces, virial, loss, d_linear, d_radial, d_shift, b->gs);
+    run_impl(b, e_target, f_target, ebar, fbar, energy, forces, virial, loss, d_linear, d_radial, d_shift, b->gs);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(b->gs, &graph);
     b->m->prof.on = prof;
@@ -412,6 +443,8 @@ int mtp_batch_run(mtp_batch* b, const double* e_target, const double* f_target, 
   HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
   return MTP_OK;
 }
+
+extern "C" {
 
 // Autotuner: time every (order, chunk) schedule on this batch (forward + loss gradient, zero
 // targets), keep the fastest; cache_path (text lines "key sorted chunk") makes the pick
@@ -459,10 +492,12 @@ int mtp_batch_tune(mtp_batch* b, const char* cache_path, int* choice, void* stre
       if (ch > 0 && ch >= b->n) continue;
       if ((rc = set_schedule(b, so, ch))) return rc;
       const double* z = (const double*)b->zeros.p;
-      run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p, (double*)ds.p, s);
+      run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p,
+               (double*)ds.p, s);
       HIP_TRY(hipEventRecord(e0, s));
       for (int r = 0; r < 2; ++r)
-        run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p, (double*)ds.p, s);
+        run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p,
+               (double*)ds.p, s);
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;

@@ -34,12 +34,10 @@ __global__ __launch_bounds__(kNT) void k_gather(const int* __restrict__ off, con
         fy += g[3L * p + 1];
         fz += g[3L * p + 2];
       }
-      const long q = rev[p];
-      if (q >= 0 && q < npairs) {  // a list not made by this library may lack mirrors
-        fx -= g[3 * q];
-        fy -= g[3 * q + 1];
-        fz -= g[3 * q + 2];
-      }
+      const long q = rev[p];  // every mirror exists: built here or validated on entry
+      fx -= g[3 * q];
+      fy -= g[3 * q + 1];
+      fz -= g[3 * q + 2];
     }
   }
 #pragma unroll
@@ -195,7 +193,57 @@ __global__ void k_pair_links(const int* __restrict__ off, const int* __restrict_
     if (t < nsp) pfirst[(long)i * nsp + t] = last[t];
 }
 
+// Consistency of a caller-supplied CSR list, one lane per atom; any failure sets *bad.
+// Checked: off[0] = 0 and off[n] = npairs, each row inside [0, npairs] and non-decreasing,
+// 0 <= j < n, species in [0, nsp), and for every pair p of row i the mirror q = rev[p] lies in
+// row j[p], points back at i with the negated shift, and has rev[q] = p.  Every read is
+// bounds-checked first, so any list is safe to check.
+__global__ __launch_bounds__(kNT) void k_check_nlist(const int* __restrict__ off, const int* __restrict__ nj,
+                                                     const int* __restrict__ shift, const int* __restrict__ rev,
+                                                     const int* __restrict__ species, int n, long long npairs,
+                                                     int nsp, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int err = 0;
+  if (i == 0 && (off[0] != 0 || (long long)off[n] != npairs)) err = 1;
+  const int z = species[i];
+  if (z < 0 || z >= nsp) err = 1;
+  const long long p0 = off[i], p1 = off[i + 1];
+  if (p0 < 0 || p1 < p0 || p1 > npairs) {
+    err = 1;
+  } else {
+    for (long long p = p0; p < p1; ++p) {
+      const int jj = nj[p];
+      if (jj < 0 || jj >= n) {
+        err = 1;
+        break;
+      }
+      const long long q = rev[p];
+      const long long r0 = off[jj], r1 = off[jj + 1];
+      if (q < r0 || q >= r1 || q < 0 || q >= npairs) {
+        err = 1;
+        break;
+      }
+      int a1, a2, a3, b1, b2, b3;
+      unpack_shift(shift[p], a1, a2, a3);
+      unpack_shift(shift[q], b1, b2, b3);
+      if (nj[q] != i || rev[q] != p || a1 != -b1 || a2 != -b2 || a3 != -b3) {
+        err = 1;
+        break;
+      }
+    }
+  }
+  if (err) atomicOr(bad, 1);
+}
+
 }  // namespace
+
+void launch_check_nlist(const int* off, const int* nj, const int* shift, const int* rev, const int* species,
+                        int n, long long npairs, int nsp, int* bad, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_check_nlist, dim3((n + kNT - 1) / kNT), dim3(kNT), 0, s, off, nj, shift, rev, species, n,
+                     npairs, nsp, bad);
+}
 
 void launch_pair_links(const int* off, const int* nj, const int* species, int nsp, int n, int* plink,
                        int* pfirst, hipStream_t s) {

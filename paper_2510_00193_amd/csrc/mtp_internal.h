@@ -128,6 +128,10 @@ void launch_grade(const double* B, long ld, int n, const double* ainv, int na, i
                   double* grade, hipStream_t s);
 void launch_max(const double* x, long n, double* out, hipStream_t s);
 // zp[p] = species of neighbour nj[p], clamped to [0, nsp)
+// *bad |= 1 when the CSR list (off, nj, shift, rev) of n atoms and npairs pairs is inconsistent
+// or a species lies outside [0, nsp) (*bad is not cleared here)
+void launch_check_nlist(const int* off, const int* nj, const int* shift, const int* rev, const int* species,
+                        int n, long long npairs, int nsp, int* bad, hipStream_t s);
 void launch_pair_links(const int* off, const int* nj, const int* species, int nsp, int n, int* plink,
                        int* pfirst, hipStream_t s);
 // out[0] = max_k |(b . ainv)_k| for one descriptor b [na]

@@ -294,10 +294,12 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
       for (int k = 0; k < 3; ++k) fown[3L * i + k] = accumulate ? fown[3L * i + k] + fo[k] : fo[k];
     }
   }
+  // with accumulate, the launches of the moment groups run one after another on one stream and
+  // each adds its share to the same per-workgroup partial
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const double s = block_sum<kLaneBlock>(w[k], red);
-    if (threadIdx.x == 0) wpart[6L * b + k] = s;
+    if (threadIdx.x == 0) wpart[6L * b + k] = accumulate ? wpart[6L * b + k] + s : s;
   }
 }
 

@@ -115,3 +115,74 @@ def test_batch_graph_replay_schedules_and_parameter_update():
     o = b.run(b.outputs(), e0, f0)
     torch.cuda.synchronize()
     assert rel_err(o["energy"].cpu().numpy(), e_ref) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def workload5():
+    from paper_2510_00193_amd import level_info
+    info = level_info(20)
+    return wl.workload(5, info["n_alpha"], info["n_mu"])
+
+
+def _sample_configs(structs):
+    """One configuration per size bucket, including the largest (256-atom) cells."""
+    ns = np.array([s.n_atoms for s in structs])
+    picks = []
+    for lo, hi in ((8, 40), (100, 140), (250, 257)):
+        idx = np.nonzero((ns >= lo) & (ns < hi))[0]
+        picks.append(int(idx[0]))
+    return picks
+
+
+@pytest.mark.timeout(600)
+def test_full_batch_sampled_configurations(workload5):
+    """The 4096-configuration level-20 batch as the benchmark runs it (graph replay): energies,
+    forces and virials of sampled configurations against the oracle, and the loss gradient with
+    targets chosen so that only sampled configurations contribute (every other configuration's
+    target is its own output, so its cotangents are exactly zero)."""
+    from paper_2510_00193_amd import Batch, Potential
+    structs, p = workload5["structures"], workload5["params"]
+    off, pos, species, cells = wl.batch_arrays(structs)
+    picks = _sample_configs(structs)
+    print(f"[batch 4096 L20] {off[-1]} atoms, sampled {picks} "
+          f"({[structs[c].n_atoms for c in picks]} atoms)", flush=True)
+    pot = Potential.from_params(p)
+    b = Batch(pot, off, torch.as_tensor(pos, device="cuda"), torch.as_tensor(species, device="cuda"), cells)
+    b.tune()
+    fwd = b.run(b.outputs(loss=False), use_graph=True)
+    torch.cuda.synchronize()
+    e_all = fwd["energy"].cpu().numpy().copy()
+    f_all = fwd["forces"].cpu().numpy().copy()
+    w_all = fwd["virial"].cpu().numpy().copy()
+    model = om.Model.from_params(p)
+    tmodel = om.Model.from_params(workload5["extra"]["target_params"])
+    e0, f0 = e_all.copy(), f_all.copy()
+    grads = [np.zeros(np.shape(p.linear)), np.zeros(np.shape(p.radial)), np.zeros(np.shape(p.shift))]
+    loss_ref = 0.0
+    for c in picks:
+        s = structs[c]
+        a0, a1 = off[c], off[c + 1]
+        nl = onb.neighbor_csr(s.pos, s.cell, p.r_cut)
+        ref = om.energy_forces_virial(model, s, nl)
+        errs = (rel_err(e_all[c], float(ref["E"].detach())), rel_err(f_all[a0:a1], ref["F"].detach().numpy()),
+                rel_err(w_all[c], ref["W"].detach().numpy()))
+        print(f"  cfg {c} N={s.n_atoms}: E {errs[0]:.2e} F {errs[1]:.2e} W {errs[2]:.2e}", flush=True)
+        assert max(errs) < 1e-10
+        if s.n_atoms > 140:
+            continue  # the oracle's gradient of a 256-atom level-20 cell takes too long here
+        tgt = om.energy_forces_virial(tmodel, s, nl)
+        e0[c] = float(tgt["E"].detach())
+        f0[a0:a1] = tgt["F"].detach().numpy()
+        de = float(ref["E"].detach()) - e0[c]
+        df = ref["F"].detach().numpy() - f0[a0:a1]
+        loss_ref += de * de + float((df * df).sum())
+        for acc, g in zip(grads, om.param_vjp(model, s, 2 * de, 2 * df, nl)):
+            acc += g
+    out = b.outputs()
+    b.run(out, torch.as_tensor(e0, device="cuda"), torch.as_tensor(f0, device="cuda"), use_graph=True)
+    torch.cuda.synchronize()
+    assert rel_err(float(out["loss"].cpu()), loss_ref) < 1e-9
+    for name, acc in zip(("d_linear", "d_radial", "d_shift"), grads):
+        err = rel_err(out[name].cpu().numpy(), acc)
+        print(f"  {name}: rel err {err:.2e}", flush=True)
+        assert err < 1e-9, name

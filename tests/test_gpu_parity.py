@@ -165,3 +165,51 @@ def test_cell_list_densities(a, rep, r_cut):
     nl = pot.neighbors(d_pos, d_sp, s.cell)
     torch.cuda.synchronize()
     _check_nlist(nl, ref)
+
+
+def test_caller_built_list_is_validated():
+    """A list assembled by the caller (not by the library) is checked before use: a correct one
+    gives the oracle's results, and each kind of inconsistency is refused with MTP_ERR_ARG."""
+    from paper_2510_00193_amd import NeighborList
+    from paper_2510_00193_amd._lib import MtpError
+    s, p = small_lattice(1501, (3, 3, 3), 3.16, 0.08, 10, 2)
+    ref_nl = onb.neighbor_csr(s.pos, s.cell, p.r_cut)
+    ref = om.energy_forces_virial(om.Model.from_params(p), s, ref_nl)
+    pot = _pot(p)
+    pos, sp = _dev(s)
+
+    def nlist(off, j, shift, rev):
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32), device="cuda")  # noqa: E731
+        return NeighborList(t(off), t(j), t(shift), t(rev))
+
+    base = (ref_nl["off"], ref_nl["j"], ref_nl["shift"], ref_nl["rev"])
+    print(f"[caller list] N={s.n_atoms} pairs={len(ref_nl['j'])}", flush=True)
+    out = pot.compute(pos, sp, s.cell, nlist=nlist(*base))
+    torch.cuda.synchronize()
+    assert rel_err(out["forces"].cpu().numpy(), ref["F"].detach().numpy()) < TOL_F
+    assert rel_err(out["virial"].cpu().numpy(), ref["W"].detach().numpy()) < TOL_W
+    bad_cases = {}
+    rev = base[3].copy()
+    rev[5] = -1
+    bad_cases["missing mirror"] = (base[0], base[1], base[2], rev)
+    rev = base[3].copy()
+    rev[5], rev[6] = rev[6], rev[5]
+    bad_cases["swapped mirrors"] = (base[0], base[1], base[2], rev)
+    off = base[0].copy()
+    off[-1] -= 1
+    bad_cases["short last row"] = (off, base[1], base[2], base[3])
+    j = base[1].copy()
+    j[3] = s.n_atoms
+    bad_cases["partner out of range"] = (base[0], j, base[2], base[3])
+    sh = base[2].copy()
+    sh[7] ^= 1
+    bad_cases["unmirrored shift"] = (base[0], base[1], sh, base[3])
+    for name, lists in bad_cases.items():
+        with pytest.raises(MtpError) as ei:
+            pot.compute(pos, sp, s.cell, nlist=nlist(*lists))
+        assert ei.value.code == 1, name
+    bad_sp = sp.clone()
+    bad_sp[2] = p.n_species
+    with pytest.raises(MtpError) as ei:
+        pot.compute(pos, bad_sp, s.cell, nlist=nlist(*base))
+    assert ei.value.code == 1

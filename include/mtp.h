@@ -149,6 +149,24 @@ int mtp_neighbors(mtp_model* m, const mtp_system* sys, int* off, int* j, int* sh
 int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double* energy,
                 double* e_atom, double* forces, double* virial, void* stream);
 
+/* mtp_compute without allocation, for callers that cannot allocate device memory (code under
+ * stream capture into a graph, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results as mtp_compute (bit-identical), except:
+ *   - nl is required (building a list allocates); an unchecked list is validated as in
+ *     mtp_compute, which synchronizes, so callers that capture pass a checked list;
+ *   - every intermediate lives in one fixed 64 MiB device scratch area per GPU, reserved when
+ *     the library is loaded and held until the process ends.  At level 16 that is about
+ *     20,000 atoms in one chunk; larger systems run in smaller chunks of the model's atoms down
+ *     to 64, and a system whose pair gradients and per-atom sums alone do not fit (about
+ *     90,000 atoms at level 16) returns MTP_ERR_CAPACITY before anything is enqueued;
+ *   - all calls on one GPU share the area and it keeps the last call's contents: calls that
+ *     overlap on one GPU (two streams, two threads, two models) race and must be serialized
+ *     by the caller;
+ *   - profiling (mtp_profile) does not time this call.
+ * No hipMalloc, hipFree or memset is issued; the work is kernel launches on the stream. */
+int mtp_compute_static(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, double* energy,
+                       double* e_atom, double* forces, double* virial, void* stream);
+
 /* Neighbourhood-mode extrapolation grade (Section 2.3 of the paper):
  *   grade [N] (device) = max_k |(B_i Ainv)_k|, grade_max [1] (device) = max_i grade_i.
  * ainv: device [n_alpha][n_alpha] row-major.  mode: MTP_GRADE_FP64 or MTP_GRADE_FP32SPLIT.

@@ -25,7 +25,7 @@ MTP_GRADE_FP32SPLIT = 1
 
 EXPORTS = ("mtp_batch_create", "mtp_batch_run", "mtp_batch_vjp", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
            "mtp_batch_neighbors", "mtp_batch_destroy", "mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset", "mtp_create", "mtp_destroy", "mtp_last_error", "mtp_sizes", "mtp_set_params",
-           "mtp_neighbors", "mtp_compute", "mtp_grade", "mtp_grade_config", "mtp_param_grad")
+           "mtp_neighbors", "mtp_compute", "mtp_compute_static", "mtp_grade", "mtp_grade_config", "mtp_param_grad")
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -103,6 +103,8 @@ def open_library(path: str):
     lib.mtp_set_params.argtypes = [vp, vp, vp, vp, i, vp]
     lib.mtp_neighbors.argtypes = [vp, ctypes.POINTER(MtpSystem), vp, vp, vp, vp, ll, ctypes.POINTER(ll), vp]
     lib.mtp_compute.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), vp, vp, vp, vp, vp]
+    lib.mtp_compute_static.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), vp, vp, vp, vp,
+                                       vp]
     if hasattr(lib, "mtp_grade"):
         lib.mtp_grade.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), vp, i, vp, vp, vp]
     if hasattr(lib, "mtp_grade_config"):
@@ -125,7 +127,7 @@ def open_library(path: str):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset",
                  "mtp_create", "mtp_sizes", "mtp_set_params", "mtp_neighbors", "mtp_compute",
-                 "mtp_grade", "mtp_grade_config", "mtp_param_grad"):
+                 "mtp_compute_static", "mtp_grade", "mtp_grade_config", "mtp_param_grad"):
         if hasattr(lib, name):
             getattr(lib, name).restype = ctypes.c_int
     return lib

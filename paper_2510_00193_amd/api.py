@@ -179,6 +179,16 @@ class Potential:
         return NeighborList(off, j[:p], sh[:p], rev[:p], checked=True)
 
     def compute(self, pos, species, cell, nlist=None, forces=True, virial=True, e_atom=False):
+        return self._compute(self._lib.mtp_compute, pos, species, cell, nlist, forces, virial, e_atom)
+
+    def compute_static(self, pos, species, cell, nlist, forces=True, virial=True, e_atom=False):
+        """compute() through mtp_compute_static: the library's fixed scratch area instead of its
+        workspace (the caller's list is required; outputs are still allocated here by torch)."""
+        if nlist is None:
+            raise ValueError("compute_static needs a neighbour list")
+        return self._compute(self._lib.mtp_compute_static, pos, species, cell, nlist, forces, virial, e_atom)
+
+    def _compute(self, entry, pos, species, cell, nlist, forces, virial, e_atom):
         sysc, n = self._system(pos, species, cell)
         dev = pos.device
         e = torch.empty(1, dtype=torch.float64, device=dev)
@@ -186,8 +196,7 @@ class Potential:
         f = torch.empty((n, 3), dtype=torch.float64, device=dev) if forces else None
         w = torch.empty(6, dtype=torch.float64, device=dev) if virial else None
         nl = ctypes.byref(nlist._c()) if nlist is not None else None
-        check(self._lib.mtp_compute(self._h, ctypes.byref(sysc), nl, _ptr(e), _ptr(ea), _ptr(f), _ptr(w),
-                                    _stream()))
+        check(entry(self._h, ctypes.byref(sysc), nl, _ptr(e), _ptr(ea), _ptr(f), _ptr(w), _stream()))
         out = {"energy": e[0]}
         if forces:
             out["forces"] = f

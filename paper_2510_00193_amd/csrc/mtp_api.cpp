@@ -216,6 +216,10 @@ int mtp_create(const mtp_params* p, mtp_model** out) {
     return mtp_fail(MTP_ERR_HIP, "copying coefficients failed");
   }
   m->nbr = nbr_work_create();
+  if ((rc = static_scratch_resolve(&m->static_scratch))) {
+    mtp_destroy(m);
+    return rc;
+  }
   *out = m;
   return MTP_OK;
 }
@@ -249,7 +253,7 @@ int mtp_set_params(mtp_model* m, const double* radial, const double* linear, con
 
 }  // extern "C"
 
-static int check_system(const mtp_model* m, const mtp_system* sys) {
+int check_system(const mtp_model* m, const mtp_system* sys) {
   if (!m || !sys) return mtp_fail(MTP_ERR_ARG, "null model or system");
   if (sys->n_atoms < 0) return mtp_fail(MTP_ERR_ARG, "n_atoms < 0");
   if (sys->n_atoms > 0 && (!sys->pos || !sys->species))
@@ -310,9 +314,10 @@ extern "C" int mtp_neighbors(mtp_model* m, const mtp_system* sys, int* off, int*
   return build_neighbors(m, sys, off, j, shift, rev, cap, n_pairs, false, (hipStream_t)stream);
 }
 
-// Resolve the list to use: the caller's, or a freshly built internal one.
+// Resolve the list to use: the caller's, or a freshly built internal one.  flag: a device word
+// for the check of a caller's list, or NULL to use the model's own.
 int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_nlist* out,
-                  hipStream_t s) {
+                  hipStream_t s, int* flag) {
   if (nl) {
     if (!nl->off || (nl->n_pairs > 0 && (!nl->j || !nl->shift || !nl->rev)) || nl->n_pairs < 0)
       return mtp_fail(MTP_ERR_ARG, "incomplete neighbour list");
@@ -320,14 +325,17 @@ int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_
     if (!nl->checked) {
       if (sys->n_atoms == 0 && nl->n_pairs != 0) return mtp_fail(MTP_ERR_ARG, "pairs in an empty system");
       if (sys->n_atoms > 0) {
-        int rc = m->flag.reserve(sizeof(int));
-        if (rc) return rc;
+        if (!flag) {
+          int rc = m->flag.reserve(sizeof(int));
+          if (rc) return rc;
+          flag = (int*)m->flag.p;
+        }
         int bad = 0;
-        HIP_TRY(hipMemsetAsync(m->flag.p, 0, sizeof(int), s));
+        launch_fill_int(flag, 1, 0, s);
         launch_check_nlist(nl->off, nl->j, nl->shift, nl->rev, sys->species, sys->n_atoms, nl->n_pairs, m->nsp,
-                           (int*)m->flag.p, s);
+                           flag, s);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(&bad, m->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (bad)
           return mtp_fail(MTP_ERR_ARG, "inconsistent neighbour list (offsets, partner index, mirror or shift) "
@@ -373,32 +381,49 @@ SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist
   return a;
 }
 
+long chain_wpart_blocks(int n, int chunk) {
+  return ((long)n + kLaneBlockHost - 1) / kLaneBlockHost + (n / std::max(chunk, 1) + 1);
+}
+
+int chain_work_reserve(mtp_model* m, int n, long long npairs, bool backward, ChainWork* w) {
+  const LevelOps& L = m->ops;
+  const int chunk = std::max(1, std::min(m->chunk, std::max(n, 1)));
+  int rc;
+  if ((rc = m->mom.reserve((size_t)L.nmom * chunk * sizeof(double))) ||
+      (rc = m->cbar.reserve((size_t)L.ncomp * chunk * sizeof(double))))
+    return rc;
+  *w = ChainWork{};
+  w->chunk = chunk;
+  w->mom = m->mom.p;
+  w->cbar = m->cbar.p;
+  if (backward) {
+    if ((rc = m->mbar.reserve((size_t)L.nmom * chunk * sizeof(double))) ||
+        (rc = m->g.reserve((size_t)std::max<long long>(npairs, 1) * 3 * sizeof(double))) ||
+        (rc = m->fown.reserve((size_t)std::max(n, 1) * 3 * sizeof(double))) ||
+        (rc = m->wpart.reserve((size_t)chain_wpart_blocks(n, chunk) * 6 * sizeof(double))))
+      return rc;
+    w->mbar = m->mbar.p;
+    w->g = (double*)m->g.p;
+    w->fown = (double*)m->fown.p;
+    w->wpart = (double*)m->wpart.p;
+  }
+  return MTP_OK;
+}
+
 // Forward (moments, contractions, energies) and optionally the adjoint chain down to the
-// per-pair gradients g and per-workgroup virial partials, chunk by chunk.
+// per-pair gradients g and per-workgroup virial partials, chunk by chunk, in the buffers of w.
 int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,
                      bool backward, double* bvals, hipStream_t s,
-                     const std::function<void(int, int)>& after_forward) {
+                     const std::function<void(int, int)>& after_forward, ChainWork& w) {
   const LevelOps& L = m->ops;
   const ChainOps& K = L.chain[m->precision == MTP_FP32_MOMENTS ? 1 : 0];
   const int n = sys->n_atoms;
-  const int chunk = std::max(1, std::min(m->chunk, std::max(n, 1)));
+  const int chunk = w.chunk;
   const long ld = chunk;
-  int rc;
-  if ((rc = m->mom.reserve((size_t)L.nmom * ld * sizeof(double))) ||
-      (rc = m->cbar.reserve((size_t)L.ncomp * ld * sizeof(double))))
-    return rc;
-  if (backward) {
-    const long nblocks = ((long)n + kLaneBlockHost - 1) / kLaneBlockHost + (n / chunk + 1);
-    if ((rc = m->mbar.reserve((size_t)L.nmom * ld * sizeof(double))) ||
-        (rc = m->g.reserve((size_t)std::max<long long>(nl.n_pairs, 1) * 3 * sizeof(double))) ||
-        (rc = m->fown.reserve((size_t)std::max(n, 1) * 3 * sizeof(double))) ||
-        (rc = m->wpart.reserve((size_t)nblocks * 6 * sizeof(double))))
-      return rc;
-  }
   SysArgs a = make_sys_args(m, sys, nl);
-  void* mom = m->mom.p;
-  void* cbar = m->cbar.p;
-  void* mbar = m->mbar.p;
+  void* mom = w.mom;
+  void* cbar = w.cbar;
+  void* mbar = w.mbar;
   long blk = 0;
   for (int i0 = 0; i0 < n; i0 += chunk) {
     const int cn = std::min(chunk, n - i0);
@@ -415,8 +440,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       }
       {
         ProfScope ps(&m->prof, P_BACKWARD, s);
-        K.backward(0, a, i0, cn, mbar, ld, (double*)m->g.p, 0, (double*)m->wpart.p + 6 * blk, nullptr,
-                   (double*)m->fown.p, s);
+        K.backward(0, a, i0, cn, mbar, ld, w.g, 0, w.wpart + 6 * blk, nullptr, w.fown, s);
       }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
       continue;
@@ -434,13 +458,34 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
       }
       for (int g = 0; g < L.ngroup; ++g) {
         ProfScope ps(&m->prof, P_BACKWARD, s);
-        K.backward(g, a, i0, cn, mbar, ld, (double*)m->g.p, g > 0, (double*)m->wpart.p + 6 * blk, nullptr,
-                   (double*)m->fown.p, s);
+        K.backward(g, a, i0, cn, mbar, ld, w.g, g > 0, w.wpart + 6 * blk, nullptr, w.fown, s);
       }
       blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
     }
   }
-  m->wblocks = blk;
+  w.wblocks = blk;
+  HIP_TRY(hipGetLastError());
+  return MTP_OK;
+}
+
+// Energy reduction, force gather and virial reduction after the chain (part: 6 kSumParts doubles).
+int finish_compute(mtp_model* m, const mtp_nlist& nl, int n, const double* ea, const ChainWork& w,
+                   double* part, double* energy, double* forces, double* virial, hipStream_t s) {
+  if (energy) {
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_sum_parts(ea, n, 1, 1, part, energy, s);
+  }
+  if (forces && n > 0) {
+    ProfScope ps(&m->prof, P_GATHER, s);
+    launch_gather_forces(nl.off, nl.rev, w.g, w.fown, n, nl.n_pairs, forces, s);
+  }
+  if (virial) {
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    if (n > 0)
+      launch_sum_parts(w.wpart, w.wblocks, 6, 6, part, virial, s);
+    else
+      launch_fill(virial, 6, 0.0, s);
+  }
   HIP_TRY(hipGetLastError());
   return MTP_OK;
 }
@@ -460,29 +505,13 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
     ea = (double*)m->eatom.p;
   }
   const bool backward = forces || virial;
+  ChainWork w;
+  if ((rc = chain_work_reserve(m, n, use.n_pairs, backward, &w))) return rc;
   if (n > 0) {
-    if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s, nullptr))) return rc;
+    if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s, nullptr, w))) return rc;
   }
   if ((rc = m->scratch.reserve(6 * kSumParts * sizeof(double)))) return rc;
-  double* part = (double*)m->scratch.p;
-  if (energy) {
-    ProfScope ps(&m->prof, P_REDUCE, s);
-    launch_sum_parts(ea, n, 1, 1, part, energy, s);
-  }
-  if (forces && n > 0) {
-    ProfScope ps(&m->prof, P_GATHER, s);
-    launch_gather_forces(use.off, use.rev, (const double*)m->g.p, (const double*)m->fown.p, n, use.n_pairs,
-                         forces, s);
-  }
-  if (virial) {
-    ProfScope ps(&m->prof, P_REDUCE, s);
-    if (n > 0)
-      launch_sum_parts((const double*)m->wpart.p, m->wblocks, 6, 6, part, virial, s);
-    else
-      HIP_TRY(hipMemsetAsync(virial, 0, 6 * sizeof(double), s));
-  }
-  HIP_TRY(hipGetLastError());
-  return MTP_OK;
+  return finish_compute(m, use, n, ea, w, (double*)m->scratch.p, energy, forces, virial, s);
 }
 
 extern "C" int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
@@ -503,10 +532,12 @@ extern "C" int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* n
     return rc;
   double* bv = (double*)m->bvals.p;
   if (n > 0) {
+    ChainWork w;
+    if ((rc = chain_work_reserve(m, n, use.n_pairs, false, &w))) return rc;
     rc = run_energy_chain(m, sys, use, (double*)m->eatom.p, false, bv, s, [&](int i0, int cn) {
       ProfScope ps(&m->prof, P_GRADE, s);
       launch_grade(bv, ld, cn, ainv, na, mode == MTP_GRADE_FP32SPLIT, grade + i0, s);
-    });
+    }, w);
     if (rc) return rc;
     ProfScope ps(&m->prof, P_REDUCE, s);
     launch_max(grade, n, grade_max, s);
@@ -546,11 +577,13 @@ extern "C" int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_n
   double* desc = descriptor ? descriptor : part + nchunks * na;
   if (n > 0) {
     long chunk = 0;
+    ChainWork w;
+    if ((rc = chain_work_reserve(m, n, use.n_pairs, false, &w))) return rc;
     rc = run_energy_chain(m, sys, use, (double*)m->eatom.p, false, bv, s, [&](int, int cn) {
       ProfScope ps(&m->prof, P_REDUCE, s);
       launch_rowsum(bv, ld, 1, cn, na, part + chunk * na, 1, s);
       ++chunk;
-    });
+    }, w);
     if (rc) return rc;
     ProfScope ps(&m->prof, P_REDUCE, s);
     launch_rowsum(part, 1, na, nchunks, na, desc, 1, s);

@@ -61,15 +61,39 @@ struct mtp_model {
   DevBuf plink, pfirst;                                 // per-species pair chains (adjoint)
   DevBuf scratch;
   DevBuf flag;                                          // status word of the list check
-  long wblocks = 0;
+  void* static_scratch = nullptr;                       // device address of the fixed scratch area
   mtp::NbrWork* nbr = nullptr;
   Profiler prof;
 };
 
 int mtp_fail(int code, const std::string& msg);
 int resolve_nlist(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, mtp_nlist* out,
-                  hipStream_t s);
+                  hipStream_t s, int* flag = nullptr);
 mtp::SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist& nl);
+// Buffers of the energy chain: moments, contraction adjoints and moment adjoints per chunk atom
+// ([entry][chunk] layout), per-pair gradients g [P][3], own force sums [N][3] and the
+// per-workgroup virial partials; wblocks is the number of partials the chain wrote.
+struct ChainWork {
+  void* mom = nullptr;
+  void* cbar = nullptr;
+  void* mbar = nullptr;
+  double* g = nullptr;
+  double* fown = nullptr;
+  double* wpart = nullptr;
+  int chunk = 1;
+  long wblocks = 0;
+};
+// upper bound of the virial partials the chain writes for n atoms in chunks of `chunk`
+long chain_wpart_blocks(int n, int chunk);
+// chain buffers from the model's grow-only workspace
+int chain_work_reserve(mtp_model* m, int n, long long npairs, bool backward, ChainWork* w);
 int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,
                      bool backward, double* bvals, hipStream_t s,
-                     const std::function<void(int, int)>& after_forward);
+                     const std::function<void(int, int)>& after_forward, ChainWork& w);
+int finish_compute(mtp_model* m, const mtp_nlist& nl, int n, const double* ea, const ChainWork& w,
+                   double* part, double* energy, double* forces, double* virial, hipStream_t s);
+int check_system(const mtp_model* m, const mtp_system* sys);
+// device address of the library's fixed scratch area on the current device (resolved once per
+// device), and its size in bytes
+int static_scratch_resolve(void** ptr);
+size_t static_scratch_bytes();

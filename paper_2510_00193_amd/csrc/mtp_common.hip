@@ -236,7 +236,27 @@ __global__ __launch_bounds__(kNT) void k_check_nlist(const int* __restrict__ off
   if (err) atomicOr(bad, 1);
 }
 
+__global__ __launch_bounds__(kNT) void k_fill(double* __restrict__ x, long n, double v) {
+  const long i = (long)blockIdx.x * kNT + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ __launch_bounds__(kNT) void k_fill_int(int* __restrict__ x, long n, int v) {
+  const long i = (long)blockIdx.x * kNT + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 }  // namespace
+
+void launch_fill(double* x, long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s, x, n, v);
+}
+
+void launch_fill_int(int* x, long n, int v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s, x, n, v);
+}
 
 void launch_check_nlist(const int* off, const int* nj, const int* shift, const int* rev, const int* species,
                         int n, long long npairs, int nsp, int* bad, hipStream_t s) {

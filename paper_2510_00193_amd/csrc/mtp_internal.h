@@ -102,6 +102,9 @@ NbrWork* nbr_work_create();
 void nbr_work_destroy(NbrWork* w);
 
 // level-independent kernels (mtp_common.hip)
+// x[0..n) = v by a kernel (no memset node when a caller captures the stream into a graph)
+void launch_fill(double* x, long n, double v, hipStream_t s);
+void launch_fill_int(int* x, long n, int v, hipStream_t s);
 // forces = (fown ? fown : own row sums of g) - mirrored gradients g[rev[p]]
 void launch_gather_forces(const int* off, const int* rev, const double* g, const double* fown, int n,
                           long long npairs, double* forces, hipStream_t s);

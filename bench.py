@@ -83,9 +83,22 @@ def measured_traffic(kernel_class, n_atoms):
     return None
 
 
-def cpu_baseline(params, target_s=12.0):
+def _cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(params, target_s=10.0, single_s=8.0):
     """The oracle on a bounded sample of the same workload: 10x10x10 bcc cells (2000 atoms)
-    drawn with the same recipe, neighbour list + E + F + virial, repeated to ~target_s."""
+    drawn with the same recipe, neighbour list + E + F + virial, repeated to ~target_s with
+    all host threads, then to ~single_s with one thread."""
     import torch
     from oracle import mtp as om
     from oracle import neighbors as onb
@@ -94,18 +107,30 @@ def cpu_baseline(params, target_s=12.0):
     pos = wl.jitter_wrap(sites, cell, 0.1, rng)
     s = wl.Structure(pos, np.zeros(len(pos), np.int32), cell)
     model = om.Model.from_params(params)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        nl = onb.neighbor_csr(s.pos, s.cell, params.r_cut)
-        om.energy_forces_virial(model, s, nl)
-        reps += 1
-        if time.perf_counter() - t0 >= target_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": s.n_atoms * reps / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+
+    def run(budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            nl = onb.neighbor_csr(s.pos, s.cell, params.r_cut)
+            om.energy_forces_virial(model, s, nl)
+            reps += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return reps, time.perf_counter() - t0
+
+    threads = torch.get_num_threads()
+    reps, dt = run(target_s)
+    torch.set_num_threads(1)
+    try:
+        reps1, dt1 = run(single_s)
+    finally:
+        torch.set_num_threads(threads)
+    return {"value": s.n_atoms * reps / dt, "unit": "atom-steps/s", "cores": threads,
+            "kind": "oracle", "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "one_thread": {"value": s.n_atoms * reps1 / dt1, "unit": "atom-steps/s", "cores": 1,
+                           "sample": f"{reps1} x the same step, {dt1:.1f} s"},
             "sample": f"{reps} x (neighbour list + E/F/virial) of a 2000-atom 10x10x10 bcc cell, "
-                      f"same recipe and level-16 coefficients, {dt:.1f} s"}
+                      f"same recipe and level-16 coefficients, {dt:.1f} s with {threads} threads"}
 
 
 def _timeit(fn, steps, warmup=1):
@@ -206,6 +231,46 @@ def section_adjoint(steps):
             "workload": f"bcc-20x20x20-2sp-L16: {s.n_atoms} atoms, VJP of (E, F) w.r.t. xi, c, s"}
 
 
+def section_small(reps=200):
+    """Small systems: latency of one E/F/virial evaluation of the 128-atom level-10 workload
+    (prebuilt list, synchronized per call), and the throughput of the 16,000-atom level-16
+    two-species workload (prebuilt list)."""
+    import torch
+    from paper_2510_00193_amd import Potential, level_info
+    out = {}
+    info = level_info(10)
+    w = wl.workload(1, info["n_alpha"], info["n_mu"])
+    (s,) = w["structures"]
+    pot = Potential.from_params(w["params"])
+    pos = torch.as_tensor(s.pos, device="cuda")
+    sp = torch.as_tensor(s.species, device="cuda")
+    nl = pot.neighbors(pos, sp, s.cell)
+    for _ in range(10):
+        pot.compute(pos, sp, s.cell, nlist=nl)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pot.compute(pos, sp, s.cell, nlist=nl)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    dt = _timeit(lambda: pot.compute(pos, sp, s.cell, nlist=nl), reps)
+    out["bcc-4x4x4-L10"] = {"atoms": s.n_atoms, "latency_us_median": float(np.median(lat) * 1e6),
+                            "latency_us_best": float(np.min(lat) * 1e6),
+                            "pipelined_us_per_eval": dt * 1e6}
+    info = level_info(16)
+    w = wl.workload(2, info["n_alpha"], info["n_mu"])
+    (s,) = w["structures"]
+    pot = Potential.from_params(w["params"])
+    pos = torch.as_tensor(s.pos, device="cuda")
+    sp = torch.as_tensor(s.species, device="cuda")
+    nl = pot.neighbors(pos, sp, s.cell)
+    dt = _timeit(lambda: pot.compute(pos, sp, s.cell, nlist=nl), 50, warmup=5)
+    out["bcc-20x20x20-2sp-L16"] = {"atoms": s.n_atoms, "ms_per_eval": dt * 1e3,
+                                   "value": s.n_atoms / dt, "unit": "atom-steps/s"}
+    return out
+
+
 def section_batch(steps, plain_sample=128):
     """4096 triclinic configurations at level 20: batched forward + loss gradient (tuned
     schedule, graph replay) against plain per-configuration launches."""
@@ -221,27 +286,39 @@ def section_batch(steps, plain_sample=128):
     dpos = torch.as_tensor(pos, device="cuda")
     dsp = torch.as_tensor(species, device="cuda")
     rng = np.random.default_rng(55)
-    e0 = torch.as_tensor(rng.normal(size=len(structs)), device="cuda")
+    e0_host = rng.normal(size=len(structs))
+    e0 = torch.as_tensor(e0_host, device="cuda")
     f0 = torch.as_tensor(rng.normal(size=(len(pos), 3)), device="cuda")
     b = Batch(pot, off, dpos, dsp, cells)
     choice = b.tune()
     out = b.outputs()
     dt = _timeit(lambda: b.run(out, e0, f0, use_graph=True), steps)
-    # plain: one configuration at a time (its own neighbour list, forward, then the VJP)
+    # plain: one configuration at a time through mtp_compute and mtp_param_grad, each with its
+    # own model and a neighbour list built before the timed region; the forward of every
+    # configuration is enqueued first, the energies come back in one synchronization (the VJP
+    # takes the energy cotangent on the host), then every VJP is enqueued
     sample = structs[:plain_sample]
-    plain = [(Potential.from_params(params), torch.as_tensor(x.pos, device="cuda"),
-              torch.as_tensor(x.species, device="cuda"), x.cell) for x in sample]
+    plain = []
+    for x in sample:
+        p1 = Potential.from_params(params)
+        ps = torch.as_tensor(x.pos, device="cuda")
+        ss = torch.as_tensor(x.species, device="cuda")
+        plain.append((p1, ps, ss, x.cell, p1.neighbors(ps, ss, x.cell)))
+    torch.cuda.synchronize()
 
     def plain_pass():
-        for k, (p1, ps, ss, cell) in enumerate(plain):
-            r = p1.compute(ps, ss, cell)
-            fb = 2.0 * (r["forces"] - f0[off[k]:off[k + 1]])
-            p1.param_grad(ps, ss, cell, 2.0 * float(r["energy"] - e0[k]), fb.contiguous())
+        outs = [p1.compute(ps, ss, cell, nlist=nl) for (p1, ps, ss, cell, nl) in plain]
+        energies = torch.stack([r["energy"] for r in outs]).cpu()
+        for k, (p1, ps, ss, cell, nl) in enumerate(plain):
+            fb = 2.0 * (outs[k]["forces"] - f0[off[k]:off[k + 1]])
+            p1.param_grad(ps, ss, cell, 2.0 * float(energies[k] - e0_host[k]), fb.contiguous(), nlist=nl)
 
     dt_plain = _timeit(plain_pass, 1)
     return {"value": len(structs) / dt, "unit": "configs/s", "ms_per_step": dt * 1e3,
             "atoms": int(off[-1]), "pairs": b.sizes()["n_pairs"], "schedule": choice,
-            "plain": {"value": len(sample) / dt_plain, "unit": "configs/s", "sample_configs": len(sample)},
+            "plain": {"value": len(sample) / dt_plain, "unit": "configs/s", "sample_configs": len(sample),
+                      "method": "mtp_compute + mtp_param_grad per configuration, prebuilt lists, one host "
+                                "synchronization per pass"},
             "speedup_vs_plain": (len(structs) / dt) / (len(sample) / dt_plain),
             "generation_s": t_gen,
             "workload": "4096 triclinic cells, N ~ U{8..256}, 3 species, level 20, n_cheb 10, r_cut 5.5: "
@@ -255,7 +332,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--rep", type=int, default=80, help="bcc repeat (80 -> 1,024,000 atoms)")
-    ap.add_argument("--sections", default="fp32,grade,adjoint,batch",
+    ap.add_argument("--sections", default="fp32,grade,adjoint,small,batch",
                     help="extra sections after the headline (comma list, or 'none')")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
@@ -370,6 +447,9 @@ def main(argv=None):
     if "adjoint" in sections:
         print("# section adjoint", file=sys.stderr, flush=True)
         out["adjoint"] = section_adjoint(args.steps)
+    if "small" in sections:
+        print("# section small", file=sys.stderr, flush=True)
+        out["small_systems"] = section_small()
     if "batch" in sections:
         print("# section batch", file=sys.stderr, flush=True)
         out["batch"] = section_batch(max(3, args.steps // 2))

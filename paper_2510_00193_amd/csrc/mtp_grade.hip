@@ -2,15 +2,21 @@
 // on the matrix cores, with the row max-abs taken in the epilogue (the product never leaves
 // registers).  B comes in [alpha][atom] layout (one chunk), Ainv is row-major n x n.
 //
-// One wave owns a tile of 16 atoms and sweeps the columns of Ainv in blocks of 8 MFMA tiles
-// (128 columns).  V_MFMA_F64_16X16X4F64 operand layout (wave64): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; its accumulator register r holds
-// D[4 r + l / 16][l % 16], r = 0..3.  The FP32-split variant splits both operands into
-// binary32 hi + lo parts, forms hi*hi + hi*lo + lo*hi with V_MFMA_F32_16X16X4F32 (same input
-// layout, but register r holds D[4 (l / 16) + r][l % 16]) and adds every K=4 partial into
-// binary64 accumulators.  Both output layouts are checked on the device by the grade parity
-// tests.
+// A workgroup of kWaves waves stages a panel of Ainv (all rows, up to kPanelBytes of columns,
+// zero-padded to whole 16x16 tiles) in LDS once and keeps it there while its waves walk their
+// 16-atom tiles (a grid of about one workgroup per CU): every MFMA takes its Ainv operand from
+// LDS and the atom operand from B, loaded kRing K steps ahead (global-memory latency is
+// several K steps of MFMA work).  Panels after the first fold
+// their row maxima into the grades already written.
+// V_MFMA_F64_16X16X4F64 operand layout (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its accumulator register r holds D[4 r + l / 16][l % 16], r = 0..3.  The
+// FP32-split variant splits both operands into binary32 hi + lo parts, forms
+// hi*hi + hi*lo + lo*hi with V_MFMA_F32_16X16X4F32 (same input layout, but register r holds
+// D[4 (l / 16) + r][l % 16]) and adds every K=4 partial into binary64 accumulators.  Both
+// output layouts are checked on the device by the grade parity tests.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "mtp_device.h"
 #include "mtp_internal.h"
@@ -18,8 +24,11 @@
 namespace mtp {
 namespace {
 
-constexpr int kWaves = 4;           // waves per workgroup, one 16-atom tile each
-constexpr int kTilesPerBlock = 8;   // 16-column MFMA tiles per column sweep
+constexpr int kWaves = 8;             // waves per workgroup (two per SIMD)
+constexpr int kMaxTiles = 8;          // 16-column MFMA tiles per column sweep
+constexpr int kPanelBytes = 120 * 1024;  // LDS panel of Ainv
+constexpr int kRing = 4;              // K steps of atom operands loaded ahead
+constexpr int kTpw = 2;               // 16-atom tiles per wave
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -31,67 +40,125 @@ __device__ __forceinline__ double max16(double v) {
   return v;
 }
 
+// One panel: columns [c_lo, c_lo + pw) of Ainv, pw a multiple of 16; kp = na rounded up to 4.
+// A wave takes kTpw 16-atom tiles at once, so every Ainv operand read from LDS feeds kTpw MFMAs.
 template <bool SPLIT>
 __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict__ B, long ld, int n,
-                                                       const double* __restrict__ ainv, int na,
-                                                       double* __restrict__ grade) {
+                                                       const double* __restrict__ ainv, int na, int c_lo,
+                                                       int pw, int first, double* __restrict__ grade) {
+  extern __shared__ double sa[];  // [kp][pw]
+  const int kp = (na + 3) & ~3;
+  for (int idx = threadIdx.x; idx < kp * pw; idx += 64 * kWaves) {
+    const int k = idx / pw, c = c_lo + idx % pw;
+    sa[idx] = (k < na && c < na) ? ainv[(long)k * na + c] : 0.0;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int tile = xcd_logical_block(blockIdx.x, gridDim.x) * kWaves + wave;
-  const int i0 = tile * 16;
-  if (i0 >= n) return;
   const int row = lane & 15;      // atom row supplied as A operand / column of D
   const int kq = lane >> 4;       // k index inside a K=4 step, and row quad of D
-  const int atom = i0 + row;
-  const bool atom_ok = atom < n;
-  double rmax[4] = {0.0, 0.0, 0.0, 0.0};
-  const int ksteps = (na + 3) / 4;
-  for (int c0 = 0; c0 < na; c0 += 16 * kTilesPerBlock) {
-    v4d acc[kTilesPerBlock];
+  const int ksteps = kp / 4;
+  const int ngroups = (n + 16 * kTpw - 1) / (16 * kTpw);
+  const int stride = gridDim.x * kWaves;
+  for (int grp = xcd_logical_block(blockIdx.x, gridDim.x) * kWaves + wave; grp < ngroups; grp += stride) {
+    const int i0 = grp * 16 * kTpw;
+    bool atom_ok[kTpw];
+    const double* bp[kTpw];
 #pragma unroll
-    for (int t = 0; t < kTilesPerBlock; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int k = ks * 4 + kq;
-      const double a = (atom_ok && k < na) ? B[(long)k * ld + atom] : 0.0;
-      float ah = 0.f, al = 0.f;
-      if (SPLIT) {
-        ah = (float)a;
-        al = (float)(a - (double)ah);
+    for (int h = 0; h < kTpw; ++h) {
+      atom_ok[h] = i0 + 16 * h + row < n;
+      bp[h] = B + i0 + 16 * h + row;
+    }
+    double rmax[kTpw][4];
+#pragma unroll
+    for (int h = 0; h < kTpw; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rmax[h][r] = 0.0;
+    for (int c0 = 0; c0 < pw; c0 += 16 * kMaxTiles) {
+      const int nt = min(kMaxTiles, (pw - c0) / 16);
+      v4d acc[kTpw][kMaxTiles];
+#pragma unroll
+      for (int h = 0; h < kTpw; ++h)
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) acc[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
+      // atom operands of the next kRing K steps in flight (one global load per lane, tile and step)
+      double ar[kTpw][kRing];
+#pragma unroll
+      for (int h = 0; h < kTpw; ++h)
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) {
+          const int k = u * 4 + kq;
+          ar[h][u] = (atom_ok[h] && k < na) ? bp[h][(long)k * ld] : 0.0;
+        }
+      for (int ks0 = 0; ks0 < ksteps; ks0 += kRing) {
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) {
+          const int ks = ks0 + u;
+          if (ks < ksteps) {
+            double a[kTpw];
+            float ah[kTpw], al[kTpw];
+            const int kn = (ks + kRing) * 4 + kq;
+#pragma unroll
+            for (int h = 0; h < kTpw; ++h) {
+              a[h] = ar[h][u];
+              ar[h][u] = (atom_ok[h] && kn < na) ? bp[h][(long)kn * ld] : 0.0;
+              ah[h] = 0.f;
+              al[h] = 0.f;
+              if (SPLIT) {
+                ah[h] = (float)a[h];
+                al[h] = (float)(a[h] - (double)ah[h]);
+              }
+            }
+            const double* srow = sa + (ks * 4 + kq) * pw + c0 + row;
+#pragma unroll
+            for (int t = 0; t < kMaxTiles; ++t) {
+              if (t < nt) {
+                const double b = srow[t * 16];
+                if (!SPLIT) {
+#pragma unroll
+                  for (int h = 0; h < kTpw; ++h)
+                    acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], b, acc[h][t], 0, 0, 0);
+                } else {
+                  const float bh = (float)b;
+                  const float bl = (float)(b - (double)bh);
+#pragma unroll
+                  for (int h = 0; h < kTpw; ++h) {
+                    v4f p = v4f{0.f, 0.f, 0.f, 0.f};
+                    p = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[h], bh, p, 0, 0, 0);
+                    v4f q = v4f{0.f, 0.f, 0.f, 0.f};
+                    q = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[h], bl, q, 0, 0, 0);
+                    q = __builtin_amdgcn_mfma_f32_16x16x4f32(al[h], bh, q, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[h][t][r] += (double)p[r] + (double)q[r];
+                  }
+                }
+              }
+            }
+          }
+        }
       }
 #pragma unroll
-      for (int t = 0; t < kTilesPerBlock; ++t) {
-        const int col = c0 + t * 16 + row;
-        const double b = (k < na && col < na) ? ainv[(long)k * na + col] : 0.0;
-        if (!SPLIT) {
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-        } else {
-          const float bh = (float)b;
-          const float bl = (float)(b - (double)bh);
-          v4f p = v4f{0.f, 0.f, 0.f, 0.f};
-          p = __builtin_amdgcn_mfma_f32_16x16x4f32(ah, bh, p, 0, 0, 0);
-          v4f q = v4f{0.f, 0.f, 0.f, 0.f};
-          q = __builtin_amdgcn_mfma_f32_16x16x4f32(ah, bl, q, 0, 0, 0);
-          q = __builtin_amdgcn_mfma_f32_16x16x4f32(al, bh, q, 0, 0, 0);
+      for (int t = 0; t < kMaxTiles; ++t) {
+        if (t < nt) {
+          const int col = c_lo + c0 + t * 16 + row;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[t][r] += (double)p[r] + (double)q[r];
+          for (int h = 0; h < kTpw; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const double v = col < na ? fabs(acc[h][t][r]) : 0.0;
+              rmax[h][r] = fmax(rmax[h][r], v);
+            }
         }
       }
     }
 #pragma unroll
-    for (int t = 0; t < kTilesPerBlock; ++t) {
-      const int col = c0 + t * 16 + row;
+    for (int h = 0; h < kTpw; ++h)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double v = col < na ? fabs(acc[t][r]) : 0.0;
-        rmax[r] = fmax(rmax[r], v);
+        const double m = max16(rmax[h][r]);
+        const int out = i0 + 16 * h + (SPLIT ? 4 * kq + r : 4 * r + kq);
+        if (row == 0 && out < n) grade[out] = first ? m : fmax(grade[out], m);
       }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const double m = max16(rmax[r]);
-    const int out = SPLIT ? i0 + 4 * kq + r : i0 + 4 * r + kq;
-    if (row == 0 && out < n) grade[out] = m;
   }
 }
 
@@ -137,13 +204,29 @@ void launch_cfg_grade(const double* b, const double* ainv, int na, double* out, 
 
 void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,
                   double* grade, hipStream_t s) {
-  if (n <= 0) return;
-  const int tiles = (n + 15) / 16;
-  const int nb = (tiles + kWaves - 1) / kWaves;
-  if (split)
-    hipLaunchKernelGGL((k_grade<true>), dim3(nb), dim3(64 * kWaves), 0, s, B, ld, n, ainv, na, grade);
-  else
-    hipLaunchKernelGGL((k_grade<false>), dim3(nb), dim3(64 * kWaves), 0, s, B, ld, n, ainv, na, grade);
+  if (n <= 0 || na <= 0) return;
+  const int kp = (na + 3) & ~3;
+  const int ncol = (na + 15) / 16 * 16;
+  int pw = (int)(kPanelBytes / (sizeof(double) * kp)) / 16 * 16;
+  pw = std::max(16, std::min(pw, ncol));
+  const int groups = (n + 16 * kTpw - 1) / (16 * kTpw);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int nb = std::max(1, std::min((groups + kWaves - 1) / kWaves, ncu));
+  const size_t lds = sizeof(double) * kp * pw;
+  static bool attr_set = false;  // allow the panel beyond the default dynamic LDS limit
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_grade<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kPanelBytes);
+    (void)hipFuncSetAttribute((const void*)k_grade<false>, hipFuncAttributeMaxDynamicSharedMemorySize, kPanelBytes);
+    attr_set = true;
+  }
+  for (int c = 0; c < ncol; c += pw) {
+    const int w = std::min(pw, ncol - c);
+    if (split)
+      hipLaunchKernelGGL((k_grade<true>), dim3(nb), dim3(64 * kWaves), lds, s, B, ld, n, ainv, na, c, w, c == 0, grade);
+    else
+      hipLaunchKernelGGL((k_grade<false>), dim3(nb), dim3(64 * kWaves), lds, s, B, ld, n, ainv, na, c, w, c == 0, grade);
+  }
 }
 
 void launch_max(const double* x, long n, double* out, hipStream_t s) {

@@ -351,24 +351,35 @@ __global__ void k_rev(long long total, const int* __restrict__ off, const int* _
   rev[p] = found;
 }
 
-// ---------------------------------------------------------------- cell path, one workgroup per bin
-// The workgroup stages the candidates of the 27 surrounding bins in LDS once: for each, its
-// position shifted by the image the bin wrap implies (for a distance filter), the key base
-// (j, wrap - image of j) and its slot in the binned arrays.  Each wave then takes one centre
-// atom of the bin:
-//   1. filter: lanes test all candidates with the shifted positions against r_cut^2 plus a
-//      margin that covers the rounding difference to the exact expression (coordinates below
-//      1e7, checked by k_bin), and compact the survivors with a ballot;
-//   2. exact: the survivors are tested with the canonical binary64 expression of
-//      pair_displacement/dist2_exact; hits are compacted into a per-wave LDS list,
-//      rank-sorted by key and written as a fixed-capacity row (rows[i * cap + k]).
-// MAXC and ROWCAP bound the staged candidates and the hits per centre; the host picks the
-// smallest instance that the density allows (LDS per workgroup sets how many workgroups share
-// a CU).  A neighbourhood beyond them, or flag[3] already raised, makes the caller take the
+// ---------------------------------------------------------------- cell path, one workgroup per brick
+// A workgroup takes a brick of BX x BY x BZ bins and stages the candidates of the brick and
+// of its one-bin halo in LDS once: for each, its position shifted by the image the halo bin's
+// wrap implies, in binary32 relative to the halo's corner, and its key base (j, wrap - image of
+// j).  Every lane then takes one centre atom of the brick; its 27 surrounding bins are 9 runs
+// of three z-consecutive halo bins, contiguous in the staged list.
+//   1. filter: the binary32 squared distance differs from the canonical binary64 expression
+//      (pair_displacement/dist2_exact) by less than a margin the host derives from the brick's
+//      extent, so candidates below r_cut^2 minus the margin are hits, those above r_cut^2 plus
+//      the margin are not, and only those in between are marked for the canonical test; the
+//      staged indices of the survivors go to the lane's list in LDS;
+//   2. the survivors' keys (partner index, hit number) are sorted in registers by a bitonic
+//      network (every partner appears once in a row when each axis has at least three bins),
+//      the marked ones take the canonical test, and the sorted row of keys (j, n1, n2, n3) is
+//      written at fixed capacity.
+// k_rows_copy then writes the CSR arrays and k_rev_unique pairs the mirrors.  A brick whose staged
+// candidates exceed MAXC, or a row beyond ROWCAP, sets flag[3] and the caller takes the
 // unstaged path.
-constexpr int kBinThreads = 256;
-constexpr int kBinWaves = kBinThreads / 64;
-constexpr double kFilterMargin = 1e-6;   // relative slack of the filter on r_cut^2
+constexpr int kBrickThreads = 256;
+constexpr int kMaxHalo = 512;     // halo bins per brick (two per thread)
+constexpr int kMaxInner = 128;    // interior bins per brick
+constexpr int kBrickMaxC = 2048;  // staged candidates per brick
+constexpr int kFilterStep = 4;    // candidates per step of the filter loop
+
+struct BrickArgs {
+  int bx[3];       // brick extent in bins
+  int nbk[3];      // bricks per axis
+  double margin;   // bound on |binary32 filter distance^2 - canonical distance^2|
+};
 
 __device__ __forceinline__ void shift_vec(int n1, int n2, int n3, const double* H, double& tx, double& ty,
                                           double& tz) {
@@ -378,210 +389,271 @@ __device__ __forceinline__ void shift_vec(int n1, int n2, int n3, const double* 
   tz = (f1 * H[2] + f2 * H[5]) + f3 * H[8];
 }
 
+// inclusive scan of v over the workgroup (kBrickThreads lanes), through sh[kBrickThreads / 64]
+__device__ __forceinline__ int block_incl_scan(int v, int* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  if (lane == 63) sh[wave] = v;
+  __syncthreads();
+  int add = 0;
+  for (int w = 0; w < wave; ++w) add += sh[w];
+  __syncthreads();
+  return v + add;
+}
+
+// ascending bitonic sort of N values held in registers (N a power of two)
+template <int N>
+__device__ __forceinline__ void bitonic_sort(unsigned* v) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const unsigned a = v[i], b = v[l];
+          const bool up = (i & k) == 0;
+          v[i] = up ? min(a, b) : max(a, b);
+          v[l] = up ? max(a, b) : min(a, b);
+        }
+      }
+}
+
 template <int MAXC, int ROWCAP>
-__global__ __launch_bounds__(kBinThreads) void k_bin_rows(PlanArgs pa, const int* __restrict__ binstart,
-                                                          const int* __restrict__ binatoms,
-                                                          const double* __restrict__ binpos,
-                                                          const int* __restrict__ binimg, int cap,
-                                                          long long* __restrict__ rows,
-                                                          int* __restrict__ counts, int* __restrict__ flag) {
-  static_assert(MAXC % 64 == 0, "staged capacity in whole waves");
-  __shared__ double px[MAXC], py[MAXC], pz[MAXC];
+__global__ __launch_bounds__(kBrickThreads) void k_brick_rows(PlanArgs pa, BrickArgs ba,
+                                                              const int* __restrict__ binstart,
+                                                              const int* __restrict__ binatoms,
+                                                              const double* __restrict__ binpos,
+                                                              const int* __restrict__ binimg,
+                                                              const double* __restrict__ pos, int cap,
+                                                              int* __restrict__ rows_j, int* __restrict__ rows_s,
+                                                              int* __restrict__ counts, int* __restrict__ flag) {
+  static_assert(ROWCAP <= 64, "hit numbers take six bits of the sort key");
+  __shared__ float xs[MAXC + kFilterStep], ys[MAXC + kFilterStep], zs[MAXC + kFilterStep];
   __shared__ long long ckey[MAXC];
-  __shared__ int cslot[MAXC];
-  static_assert(ROWCAP % 4 == 0, "padded hit lists");
-  __shared__ __align__(16) long long hits[kBinWaves][ROWCAP];
-  __shared__ unsigned short surv[kBinWaves][MAXC];
-  __shared__ int bst[27], boff[28], bwrap[27];
+  __shared__ unsigned short hl[ROWCAP][kBrickThreads];
+  __shared__ int hst[kMaxHalo], hoff[kMaxHalo + 1], hwrap[kMaxHalo];
+  __shared__ int ioff[kMaxInner + 1], ihalo[kMaxInner];
+  __shared__ int scan_sh[kBrickThreads / 64];
   __shared__ int skip;
   const int bid = blockIdx.x;
-  const int b2 = bid % pa.nb[2];
-  const int b1 = (bid / pa.nb[2]) % pa.nb[1];
-  const int b0 = bid / (pa.nb[2] * pa.nb[1]);
-  // the 27 surrounding bins (fixed order), the wrap each one implies, and their offsets in the
-  // staged list (inclusive scan across the first wave)
-  if (threadIdx.x < 64) {
-    const int nbk = threadIdx.x;
-    int cnt = 0;
-    if (nbk < 27) {
-      const int d0 = nbk / 9 - 1, d1 = (nbk / 3) % 3 - 1, d2 = nbk % 3 - 1;
-      int c0 = b0 + d0, w0 = 0, c1 = b1 + d1, w1 = 0, c2 = b2 + d2, w2 = 0;
+  const int k2 = bid % ba.nbk[2], k1 = (bid / ba.nbk[2]) % ba.nbk[1], k0 = bid / (ba.nbk[2] * ba.nbk[1]);
+  const int x0 = k0 * ba.bx[0], y0 = k1 * ba.bx[1], z0 = k2 * ba.bx[2];
+  const int ex = min(ba.bx[0], pa.nb[0] - x0), ey = min(ba.bx[1], pa.nb[1] - y0), ez = min(ba.bx[2], pa.nb[2] - z0);
+  const int hx = ex + 2, hy = ey + 2, hz = ez + 2, nh = hx * hy * hz, ni = ex * ey * ez;
+  if (threadIdx.x == 0) skip = flag[3];  // one read: the caller already falls back
+  // halo bins in (x, y, z) order with z fastest: physical bin, wrap and atom count; thread t
+  // takes halo bins 2t and 2t + 1
+  int hc[2] = {0, 0};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int h = 2 * threadIdx.x + u;
+    if (h < nh) {
+      const int a2 = h % hz, a1 = (h / hz) % hy, a0 = h / (hz * hy);
+      int c0 = x0 - 1 + a0, c1 = y0 - 1 + a1, c2 = z0 - 1 + a2, w0 = 0, w1 = 0, w2 = 0;
       if (c0 < 0) { c0 += pa.nb[0]; w0 = -1; } else if (c0 >= pa.nb[0]) { c0 -= pa.nb[0]; w0 = 1; }
       if (c1 < 0) { c1 += pa.nb[1]; w1 = -1; } else if (c1 >= pa.nb[1]) { c1 -= pa.nb[1]; w1 = 1; }
       if (c2 < 0) { c2 += pa.nb[2]; w2 = -1; } else if (c2 >= pa.nb[2]) { c2 -= pa.nb[2]; w2 = 1; }
       const int cid = (c0 * pa.nb[1] + c1) * pa.nb[2] + c2;
-      bst[nbk] = binstart[cid];
-      cnt = binstart[cid + 1] - binstart[cid];
-      bwrap[nbk] = pack_img(w0, w1, w2);
-    }
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-      const int v = __shfl_up(incl, d, 64);
-      if (nbk >= d) incl += v;
-    }
-    if (nbk < 27) boff[nbk + 1] = incl;
-    if (nbk == 0) {
-      boff[0] = 0;
-      skip = flag[3];  // one read for the whole workgroup: the caller already falls back
+      hst[h] = binstart[cid];
+      hc[u] = binstart[cid + 1] - binstart[cid];
+      hwrap[h] = pack_img(w0, w1, w2);
     }
   }
+  {
+    const int incl = block_incl_scan(hc[0] + hc[1], scan_sh);
+    if (2 * threadIdx.x < nh) hoff[2 * threadIdx.x + 1] = incl - hc[1];
+    if (2 * threadIdx.x + 1 < nh) hoff[2 * threadIdx.x + 2] = incl;
+    if (threadIdx.x == 0) hoff[0] = 0;
+  }
   __syncthreads();
-  const int ncand = boff[27];
+  const int ncand = hoff[nh];
   if (skip) return;
   if (ncand > MAXC) {
     if (threadIdx.x == 0) flag[3] = 1;
     return;
   }
-  const int npad = (ncand + 63) & ~63;  // staged list padded to whole waves with far points
-  for (int k = threadIdx.x; k < npad; k += kBinThreads) {
-    if (k >= ncand) {
-      px[k] = py[k] = pz[k] = 1e300;
-      continue;
+  // interior bins: halo index and running centre offsets
+  {
+    int c = 0;
+    if (threadIdx.x < ni) {
+      const int a2 = threadIdx.x % ez, a1 = (threadIdx.x / ez) % ey, a0 = threadIdx.x / (ez * ey);
+      const int h = ((a0 + 1) * hy + (a1 + 1)) * hz + (a2 + 1);
+      ihalo[threadIdx.x] = h;
+      c = hoff[h + 1] - hoff[h];
     }
-    int lo = 0, hi = 26;  // bin t with boff[t] <= k < boff[t + 1]
+    const int incl = block_incl_scan(c, scan_sh);
+    if (threadIdx.x < ni) ioff[threadIdx.x + 1] = incl;
+    if (threadIdx.x == 0) ioff[0] = 0;
+  }
+  // halo corner (fractional (x0 - 1, y0 - 1, z0 - 1) / nb): origin of the binary32 coordinates
+  double ox0, oy0, oz0;
+  {
+    const double f0 = (double)(x0 - 1) / pa.nb[0], f1 = (double)(y0 - 1) / pa.nb[1], f2 = (double)(z0 - 1) / pa.nb[2];
+    ox0 = (f0 * pa.H[0] + f1 * pa.H[3]) + f2 * pa.H[6];
+    oy0 = (f0 * pa.H[1] + f1 * pa.H[4]) + f2 * pa.H[7];
+    oz0 = (f0 * pa.H[2] + f1 * pa.H[5]) + f2 * pa.H[8];
+  }
+  // stage the candidates
+  for (int k = threadIdx.x; k < ncand; k += kBrickThreads) {
+    int lo = 0, hi = nh - 1;  // halo bin t with hoff[t] <= k < hoff[t + 1]
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (boff[mid] <= k) lo = mid; else hi = mid - 1;
+      if (hoff[mid] <= k) lo = mid; else hi = mid - 1;
     }
-    const int q = bst[lo] + (k - boff[lo]);
+    const int q = hst[lo] + (k - hoff[lo]);
     const int j = binatoms[q];
-    // wrap - image of j, per axis (both biased bytes)
-    const int wr = bwrap[lo], im = binimg[q];
+    const int wr = hwrap[lo], im = binimg[q];
     const int c0 = ((wr >> 16) & 0xFF) - ((im >> 16) & 0xFF);
     const int c1 = ((wr >> 8) & 0xFF) - ((im >> 8) & 0xFF);
     const int c2 = (wr & 0xFF) - (im & 0xFF);
     double tx, ty, tz;
     shift_vec(c0, c1, c2, pa.H, tx, ty, tz);
-    px[k] = binpos[3L * q] + tx;
-    py[k] = binpos[3L * q + 1] + ty;
-    pz[k] = binpos[3L * q + 2] + tz;
+    xs[k] = (float)((binpos[3L * q] + tx) - ox0);
+    ys[k] = (float)((binpos[3L * q + 1] + ty) - oy0);
+    zs[k] = (float)((binpos[3L * q + 2] + tz) - oz0);
     ckey[k] = make_key(j, c0, c1, c2);
-    cslot[k] = q;
   }
+  if (threadIdx.x < kFilterStep) xs[ncand + threadIdx.x] = ys[ncand + threadIdx.x] = zs[ncand + threadIdx.x] = 1e30f;
   __syncthreads();
-  const double rc2f = pa.rc2 * (1.0 + kFilterMargin) + kFilterMargin;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  const int a0 = binstart[bid], a1 = binstart[bid + 1];
-  long long* hw = hits[wave];
-  unsigned short* sw = surv[wave];
-  for (int ci = a0 + wave; ci < a1; ci += kBinWaves) {
-    const int i = binatoms[ci];
-    const double rix = binpos[3L * ci], riy = binpos[3L * ci + 1], riz = binpos[3L * ci + 2];
-    const int im = binimg[ci];
-    const int oi0 = ((im >> 16) & 0xFF) - 128, oi1 = ((im >> 8) & 0xFF) - 128, oi2 = (im & 0xFF) - 128;
-    double ox, oy, oz;
-    shift_vec(oi0, oi1, oi2, pa.H, ox, oy, oz);
-    const double qx = rix - ox, qy = riy - oy, qz = riz - oz;
-    // 1. filter (padding fails it; survivors compacted in candidate order)
-    int ns = 0;
-    for (int q0 = 0; q0 < npad; q0 += 64) {
-      const int q = q0 + lane;
-      const double ex = px[q] - qx, ey = py[q] - qy, ez = pz[q] - qz;
-      const bool pass = fma(ez, ez, fma(ey, ey, ex * ex)) < rc2f;
-      const unsigned long long mask = __ballot(pass);
-      if (pass) sw[ns + __popcll(mask & below)] = (unsigned short)q;
-      ns += __popcll(mask);
+  const double rc2 = pa.rc2;
+  const float rc_hi = (float)(rc2 + ba.margin), rc_lo = (float)(rc2 - ba.margin);
+  const int ncent = ioff[ni];
+  unsigned short* mylist = &hl[0][threadIdx.x];
+  for (int c = threadIdx.x; c < ncent; c += kBrickThreads) {
+    int lo = 0, hi = ni - 1;  // interior bin b with ioff[b] <= c < ioff[b + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ioff[mid] <= c) lo = mid; else hi = mid - 1;
     }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    // 2. exact test of the survivors; hits compacted into the wave's LDS list
+    const int h = ihalo[lo];
+    const int cs = hst[h] + (c - ioff[lo]);  // the centre's slot in the binned arrays
+    const int i = binatoms[cs];
+    const double rix = pos[3L * i], riy = pos[3L * i + 1], riz = pos[3L * i + 2];
+    const int im = binimg[cs];
+    const int oi0 = ((im >> 16) & 0xFF) - 128, oi1 = ((im >> 8) & 0xFF) - 128, oi2 = (im & 0xFF) - 128;
+    double sx, sy, sz;
+    shift_vec(oi0, oi1, oi2, pa.H, sx, sy, sz);
+    const float qx = (float)((rix - sx) - ox0), qy = (float)((riy - sy) - oy0), qz = (float)((riz - sz) - oz0);
     const long long self = make_key(i, 0, 0, 0);
     const long long koff = ((long long)oi0 << 16) + ((long long)oi1 << 8) + (long long)oi2;
+    const int a2 = h % hz, a1 = (h / hz) % hy, a0 = h / (hz * hy);
+    // 1. filter
     int cnt = 0;
-    for (int h0 = 0; h0 < ns; h0 += 64) {
-      const int h = h0 + lane;
-      bool hit = false;
-      long long key = 0;
-      if (h < ns) {
-        const int q = sw[h];
-        key = ckey[q] + koff;
-        if (key != self) {
-          const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
-                    n3 = (int)(key & 0xFF) - 128;
-          const long sq = cslot[q];
-          double dx, dy, dz;
-          pair_displacement(rix, riy, riz, binpos[3 * sq], binpos[3 * sq + 1], binpos[3 * sq + 2], n1, n2, n3,
-                            pa.H, dx, dy, dz);
-          hit = dist2_exact(dx, dy, dz) < pa.rc2;
+    for (int r = 0; r < 9; ++r) {
+      const int hb = ((a0 - 1 + r / 3) * hy + (a1 - 1 + r % 3)) * hz + (a2 - 1);
+      const int q1 = hoff[hb + 3];
+      // four candidates per step: their LDS reads are in flight together (reads past the run
+      // stay inside the staged list, which is padded by kFilterStep entries, and are masked)
+      for (int q = hoff[hb]; q < q1; q += kFilterStep) {
+        float dd[kFilterStep];
+#pragma unroll
+        for (int u = 0; u < kFilterStep; ++u) {
+          const float ex_ = xs[q + u] - qx, ey_ = ys[q + u] - qy, ez_ = zs[q + u] - qz;
+          dd[u] = fmaf(ez_, ez_, fmaf(ey_, ey_, ex_ * ex_));
+        }
+#pragma unroll
+        for (int u = 0; u < kFilterStep; ++u) {
+          if (q + u < q1 && dd[u] < rc_hi) {
+            if (cnt < ROWCAP)
+              mylist[cnt * kBrickThreads] = (unsigned short)((q + u) | (dd[u] >= rc_lo ? 0x8000 : 0));
+            ++cnt;
+          }
         }
       }
-      const unsigned long long mask = __ballot(hit);
-      if (hit) {
-        const int slot = cnt + __popcll(mask & below);
-        if (slot < ROWCAP) hw[slot] = key;
-      }
-      cnt += __popcll(mask);
     }
-    if (cnt > cap || cnt > ROWCAP) {
-      if (lane == 0) flag[3] = 1;
+    if (cnt > ROWCAP || cnt > cap) {
+      flag[3] = 1;
+      counts[i] = 0;
       continue;
     }
-    // 3. rank of each hit among the hits (keys are distinct) -> sorted row; the list is padded
-    // to a multiple of 4 with keys above every real key, read four at a time (broadcast)
-    const int cnt4 = (cnt + 3) & ~3;
-    if (lane < cnt4 - cnt) hw[cnt + lane] = LLONG_MAX;
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    for (int h = lane; h < cnt; h += 64) {
-      const long long k = hw[h];
-      int rank = 0;
-      for (int t = 0; t < cnt4; t += 4) {
-        const longlong2 u = *reinterpret_cast<const longlong2*>(hw + t);
-        const longlong2 v = *reinterpret_cast<const longlong2*>(hw + t + 2);
-        rank += (int)(u.x < k) + (int)(u.y < k) + (int)(v.x < k) + (int)(v.y < k);
+    // 2. keys (partner << 6 | hit number) of the hits, sorted in registers
+    unsigned v[ROWCAP];
+#pragma unroll
+    for (int t = 0; t < ROWCAP; ++t) {
+      v[t] = 0xFFFFFFFFu;
+      if (t < cnt) {  // (the bitonic network below only sorts what is set here)
+        const unsigned u = mylist[t * kBrickThreads];
+        const long long key = ckey[u & 0x7FFF] + koff;
+        bool hit = key != self;
+        if (hit && (u & 0x8000)) {  // inside the margin: the canonical expression decides
+          const int j = (int)(key >> 24);
+          const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
+                    n3 = (int)(key & 0xFF) - 128;
+          double dx, dy, dz;
+          pair_displacement(rix, riy, riz, pos[3L * j], pos[3L * j + 1], pos[3L * j + 2], n1, n2, n3, pa.H, dx, dy,
+                            dz);
+          hit = dist2_exact(dx, dy, dz) < rc2;
+        }
+        if (hit) v[t] = ((unsigned)(key >> 24) << 6) | (unsigned)t;
       }
-      rows[(long)i * cap + rank] = k;
     }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) counts[i] = cnt;
+    // sort the first 32 keys only when no lane of the wave has more hits
+    const bool small = __all(cnt <= 32);
+    if (small) bitonic_sort<32>(v);
+    else bitonic_sort<ROWCAP>(v);
+    int* rj = rows_j + (long)i * cap;
+    int* rs = rows_s + (long)i * cap;
+    int m = 0;
+#pragma unroll
+    for (int t = 0; t < ROWCAP; ++t) {
+      if ((t < 32 || !small) && v[t] != 0xFFFFFFFFu) {
+        const unsigned u = mylist[(v[t] & 63u) * kBrickThreads];
+        const long long key = ckey[u & 0x7FFF] + koff;
+        const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
+                  n3 = (int)(key & 0xFF) - 128;
+        rj[t] = (int)(key >> 24);
+        rs[t] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
+        ++m;
+      }
+    }
+    counts[i] = m;
   }
 }
 
-// CSR from the fixed-capacity rows: 32 lanes per atom copy its sorted row.  The mirror of a
-// pair (i, j, n) is (j, i, -n); the lane of the pair that owns the unordered pair (j > i, or
-// j == i and the larger packed shift) finds the mirror by binary search in row j and writes
-// rev for both entries, so every unordered pair is searched once.  The list is exactly
-// symmetric (the mirrored displacement is the exact negative), so every mirror exists.
-__global__ __launch_bounds__(256) void k_rows_to_csr(int n, int cap, const long long* __restrict__ rows,
-                                                     const int* __restrict__ counts,
-                                                     const int* __restrict__ off, int* __restrict__ nj,
-                                                     int* __restrict__ shift, int* __restrict__ rev) {
-  const int i = blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int lane = threadIdx.x & 31;
+// Sorted fixed-capacity rows -> CSR j / packed shift: G lanes per row, lane t copies entry t.
+constexpr int kCsrThreads = 256;
+template <int G, int CAP>
+__global__ __launch_bounds__(kCsrThreads) void k_rows_copy(int n, const int* __restrict__ rows_j,
+                                                           const int* __restrict__ rows_s,
+                                                           const int* __restrict__ counts,
+                                                           const int* __restrict__ off, int* __restrict__ nj,
+                                                           int* __restrict__ shift) {
+  constexpr int R = kCsrThreads / G;
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int i = b * R + threadIdx.x / G, lane = threadIdx.x % G;
   if (i >= n) return;
   const int cnt = counts[i], o = off[i];
-  for (int k = lane; k < cnt; k += 32) {
-    const long long key = rows[(long)i * cap + k];
-    const int j = (int)(key >> 24);
-    const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
-              n3 = (int)(key & 0xFF) - 128;
-    nj[o + k] = j;
-    shift[o + k] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
-    const long long want = make_key(i, -n1, -n2, -n3);
-    const bool owner = j > i || (j == i && (key & 0xFFFFFF) > (want & 0xFFFFFF));
-    if (rev && owner) {
-      const long long* rj = rows + (long)j * cap;
-      int lo = 0, hi = counts[j] - 1, found = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const long long v = rj[mid];
-        if (v == want) {
-          found = mid;
-          break;
-        }
-        if (v < want) lo = mid + 1; else hi = mid - 1;
-      }
-      if (found >= 0) {
-        const int q = off[j] + found;
-        rev[o + k] = q;
-        rev[q] = o + k;
-      } else {
-        rev[o + k] = -1;
-      }
+  for (int t = lane; t < cnt; t += G) {
+    nj[o + t] = rows_j[(long)i * CAP + t];
+    shift[o + t] = rows_s[(long)i * CAP + t];
+  }
+}
+
+// rev of a list whose rows hold each partner once (the staged path): the mirror of (i, j, n) is
+// the entry of row j whose partner is i, found by a lower bound over row j's partner indices in
+// the CSR array (4 bytes an entry, so a row spans one or two cache lines).  G lanes per row.
+template <int G>
+__global__ __launch_bounds__(kCsrThreads) void k_rev_unique(int n, const int* __restrict__ off,
+                                                            const int* __restrict__ nj, int* __restrict__ rev) {
+  constexpr int R = kCsrThreads / G;
+  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int i = b * R + threadIdx.x / G, lane = threadIdx.x % G;
+  if (i >= n) return;
+  const int p0 = off[i], p1 = off[i + 1];
+  for (int p = p0 + lane; p < p1; p += G) {
+    const int j = nj[p];
+    int lo = off[j], hi = off[j + 1];  // first entry of row j with partner >= i
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (nj[mid] < i) lo = mid + 1; else hi = mid;
     }
+    rev[p] = lo;
   }
 }
 
@@ -691,7 +763,7 @@ NbrWork* nbr_work_create() { return new NbrWork(); }
 void nbr_work_destroy(NbrWork* w) { delete w; }
 
 enum Slot { S_FRAC, S_BIN, S_IMG, S_BINCNT, S_BINSTART, S_BINFILL, S_BINATOMS, S_COUNTS, S_BSUM,
-            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG, S_ROWS, S_BINPOS, S_BINIMG, S_NSLOTS };
+            S_TOTAL, S_KEY, S_SKEY, S_ROWID, S_FLAG, S_ROWS, S_ROWS2, S_BINPOS, S_BINIMG, S_NSLOTS };
 static_assert(S_NSLOTS <= 20, "workspace slots");
 
 static void inv3(const double* H, double* I, double* det) {
@@ -783,6 +855,42 @@ static int read_back(NbrWork* w, const int* flag, long long* total, int* flags, 
   return 0;
 }
 
+// Brick extent (bins per axis) for the staged path: the largest interior whose brick plus halo
+// holds on average at most two thirds of the staged capacity, within the halo and interior
+// table sizes; false when even a single bin's neighbourhood is too dense.  Also the filter
+// margin: binary32 coordinates relative to the halo corner are bounded by the halo's extent
+// E = sum_k (bx_k + 2) / nb_k |H_k|, each carries a rounding error below 2^-24 E, so
+// |d2_32 - d2| < 2^-24 (7 r E + 3 r^2) for distances r near the cutoff; the margin is four times
+// that.
+static bool brick_shape(const int* nb, double per_bin, const double* H, double rcut, BrickArgs* ba) {
+  int best = 0;
+  for (int x = 1; x <= 8; ++x)
+    for (int y = 1; y <= 8; ++y)
+      for (int z = 1; z <= 8; ++z) {
+        if (x > nb[0] || y > nb[1] || z > nb[2]) continue;
+        const int halo = (x + 2) * (y + 2) * (z + 2), inner = x * y * z;
+        if (halo > kMaxHalo || inner > kMaxInner) continue;
+        if (halo * per_bin > (2.0 / 3.0) * kBrickMaxC) continue;
+        // prefer more centres per brick, then the more compact shape
+        const int score = inner * 64 - halo;
+        if (score > best) {
+          best = score;
+          ba->bx[0] = x;
+          ba->bx[1] = y;
+          ba->bx[2] = z;
+        }
+      }
+  if (!best) return false;
+  double ext = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    ba->nbk[k] = (nb[k] + ba->bx[k] - 1) / ba->bx[k];
+    const double len = sqrt(H[3 * k] * H[3 * k] + H[3 * k + 1] * H[3 * k + 1] + H[3 * k + 2] * H[3 * k + 2]);
+    ext += (double)(ba->bx[k] + 2) / nb[k] * len;
+  }
+  ba->margin = 4.0 * ldexp(7.0 * rcut * ext + 3.0 * rcut * rcut, -24);
+  return true;
+}
+
 int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int nsp, int n,
               const double* H, double rcut, NbrWork* w, int* off, long long* total, int* flags,
               hipStream_t s) {
@@ -808,41 +916,40 @@ int nbr_count(const NbrPlan& plan, const double* pos, const int* species, int ns
                          flag);
     int rc = scan_counts(w, bincnt, nbins, binstart, nullptr, s);
     if (rc) return rc;
-    // rows of the staged path, sized from the density (a sphere of radius r_cut, 50% slack),
-    // and the staged candidates from the atoms per bin (27 bins, 50% slack)
+    // staged path: bricks of bins sized from the density so that a brick and its halo hold
+    // about two thirds of the staged capacity; rows of 64 or 128 keys
     w->row_cap = 0;
-    int inst = 0, cap = 0;
+    BrickArgs ba{};
+    int cap = 0;
     if (n > 0) {
       const double vol = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
                               H[2] * (H[3] * H[7] - H[4] * H[6]));
       const double expect = 4.18879020478639 * rcut * rcut * rcut * n / vol;
-      cap = (int)(1.5 * expect) + 32;
-      cap = ((cap + 31) / 32) * 32;
-      const double cand = 1.5 * 27.0 * n / nbins + 32;
-      if (cap <= 128 && cand <= 512) inst = 1;
-      else if (cap <= 128 && cand <= 768) inst = 2;
-      else if (cap <= 256 && cand <= 1024) inst = 3;
+      const double need = 1.25 * expect + 16;
+      cap = need <= 64 ? 64 : (need <= 128 ? 128 : 0);
+      const double per_bin = (double)n / nbins;
+      // sorting by partner index needs every partner once per row (three bins per axis) and
+      // partner indices below 2^26 (the sort key)
+      if (plan.nb[0] < 3 || plan.nb[1] < 3 || plan.nb[2] < 3 || n >= (1 << 26)) cap = 0;
+      if (cap && !brick_shape(plan.nb, per_bin, H, rcut, &ba)) cap = 0;
     }
-    double* binpos = inst ? w->get<double>(S_BINPOS, 3L * n) : nullptr;
-    int* binimg = inst ? w->get<int>(S_BINIMG, n) : nullptr;
-    long long* rows = inst ? w->get<long long>(S_ROWS, (size_t)n * cap) : nullptr;
-    if (inst && (!binpos || !binimg || !rows)) return MTP_ERR_OOM;
+    double* binpos = cap ? w->get<double>(S_BINPOS, 3L * n) : nullptr;
+    int* binimg = cap ? w->get<int>(S_BINIMG, n) : nullptr;
+    int* rows_j = cap ? w->get<int>(S_ROWS, (size_t)n * cap) : nullptr;
+    int* rows_s = cap ? w->get<int>(S_ROWS2, (size_t)n * cap) : nullptr;
+    if (cap && (!binpos || !binimg || !rows_j || !rows_s)) return MTP_ERR_OOM;
     if (n > 0)
       hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(kNT), 0, s, n, bin, binstart, binfill, binatoms, pos, img,
                          binpos, binimg);
-    if (inst == 1)
-      hipLaunchKernelGGL((k_bin_rows<512, 128>), dim3(nbins), dim3(kBinThreads), 0, s, pa, binstart, binatoms,
-                         binpos, binimg, cap, rows, counts, flag);
-    else if (inst == 2)
-      hipLaunchKernelGGL((k_bin_rows<768, 128>), dim3(nbins), dim3(kBinThreads), 0, s, pa, binstart, binatoms,
-                         binpos, binimg, cap, rows, counts, flag);
-    else if (inst == 3)
-      hipLaunchKernelGGL((k_bin_rows<1024, 256>), dim3(nbins), dim3(kBinThreads), 0, s, pa, binstart, binatoms,
-                         binpos, binimg, cap, rows, counts, flag);
-    else if (n > 0)
+    if (cap) {
+      const int nbricks = ba.nbk[0] * ba.nbk[1] * ba.nbk[2];
+      hipLaunchKernelGGL((k_brick_rows<kBrickMaxC, 64>), dim3(nbricks), dim3(kBrickThreads), 0, s, pa, ba, binstart,
+                         binatoms, binpos, binimg, pos, cap, rows_j, rows_s, counts, flag);
+      w->row_cap = cap;
+    } else if (n > 0) {
       hipLaunchKernelGGL(k_cell_count, dim3(gb), dim3(kNT), 0, s, pos, n, pa, bin, img, binstart, binatoms,
                          counts);
-    if (inst) w->row_cap = cap;
+    }
   } else {
     double* sfrac = w->get<double>(S_FRAC, 3L * n);
     if (!sfrac) return MTP_ERR_OOM;
@@ -882,11 +989,19 @@ int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, dou
   int* rowid = w->get<int>(S_ROWID, total);
   if (!skey || !rowid) return MTP_ERR_OOM;
   if (plan.cells && w->row_cap > 0) {
-    const long long* rows = w->get<long long>(S_ROWS, 1);
+    const int* rows_j = w->get<int>(S_ROWS, 1);
+    const int* rows_s = w->get<int>(S_ROWS2, 1);
     int* counts = w->get<int>(S_COUNTS, n);
-    if (n > 0)
-      hipLaunchKernelGGL(k_rows_to_csr, dim3((n + 7) / 8), dim3(256), 0, s, n, w->row_cap, rows, counts, off, nj,
-                         shift, rev);
+    if (n > 0) {
+      if (w->row_cap == 64)
+        hipLaunchKernelGGL((k_rows_copy<32, 64>), dim3((n + 7) / 8), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
+                           counts, off, nj, shift);
+      else
+        hipLaunchKernelGGL((k_rows_copy<64, 128>), dim3((n + 3) / 4), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
+                           counts, off, nj, shift);
+      if (rev)
+        hipLaunchKernelGGL((k_rev_unique<32>), dim3((n + 7) / 8), dim3(kCsrThreads), 0, s, n, off, nj, rev);
+    }
     if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
     return 0;
   }

@@ -9,6 +9,7 @@ Modules:
   basis      brute-force enumeration of the basis functions
   neighbors  brute-force canonical periodic neighbour list
   mtp        energies, forces, virial, grade and parameter gradients
+  maxvol     active-set update by MaxVol row swaps
 
 Every function here is pinned by tests under tests/ (test_oracle_*.py)
 against closed forms, invariants, library routines and brute force.

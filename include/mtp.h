@@ -183,6 +183,22 @@ int mtp_grade(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const do
 int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, const double* ainv,
                      double* descriptor, double* grade, void* stream);
 
+/* Active-set update by MaxVol row swaps.  The paper bases the extrapolation grade on
+ * D-optimality and the MaxVol algorithm (Section 1): the active set is the n x n matrix A
+ * whose rows are the basis vectors of selected neighbourhoods (or configuration descriptors),
+ * a candidate row c has grade max_k |(c A^-1)_k|, and replacing active row k by candidate i
+ * multiplies |det A| by |(c_i A^-1)_k|.  The call runs the MaxVol iteration (Goreinov et al.,
+ * 2010): take the candidate entry of largest |(c_i A^-1)_k| (the first in row-major order
+ * among equal values); if it exceeds 1 + tol, exchange active row k and candidate row i and
+ * update A^-1 by the Sherman-Morrison formula; repeat, at most max_swaps times.
+ *   cand  device [n_cand][n], active device [n][n], ainv device [n][n] = active^-1, row-major,
+ *         all updated in place (rows exchanged, ainv kept as the inverse).
+ *   swaps host [2 * max_swaps] or NULL: the (i, k) of every swap in order; grades host
+ *         [max_swaps] or NULL: the signed (c_i A^-1)_k of every swap; *n_swaps (host) swaps done.
+ * 1 <= n <= 4096.  Synchronizes once per iteration (the host decides whether to continue). */
+int mtp_maxvol(mtp_model* m, double* cand, int n_cand, int n, double* active, double* ainv, double tol,
+               int max_swaps, int* swaps, double* grades, int* n_swaps, void* stream);
+
 /* Vector-Jacobian product of (E, F) with respect to the coefficients.  The paper keeps MLIP-3's
  * potential files and its fitting (Section 1 and Section 2.3); this call is the gradient a fit
  * needs, computed on the device:
@@ -211,11 +227,15 @@ int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, dou
  *   of output pointers) and replayed on an internal stream ordered after and before the
  *   caller's stream.  Coefficient updates through mtp_set_params(on_device = 1) reach the
  *   replays without re-capture.
- * mtp_batch_tune: times the atom-to-lane schedules (natural order or sorted by neighbour
- *   count; chunk sizes) on this batch and keeps the fastest; with cache_path (text file)
- *   the pick is read back for the same level, species, basis size and size bucket.
- *   choice (host [2], may be NULL) receives {sorted, chunk_atoms}.  Synchronizes.
- * mtp_batch_schedule: sets a schedule explicitly (sorted 0/1, chunk_atoms 0 = all atoms).
+ * mtp_batch_tune: times the schedules on this batch and keeps the fastest: atom order (natural,
+ *   or sorted by neighbour count so that a wave's lanes do similar work and the longest tiles
+ *   come first), chunk of atoms per pass, and static grids or persistent pair kernels (one
+ *   workgroup per SIMD pulling 64-atom tiles from a device counter inside the same launch
+ *   sequence, zeroed by a kernel so that graph capture stays valid); with cache_path (text
+ *   file) the pick is read back for the same level, species, Chebyshev count and size bucket.
+ *   choice (host [3], may be NULL) receives {sorted, chunk_atoms, persistent}.  Synchronizes.
+ * mtp_batch_schedule: sets a schedule explicitly (sorted 0/1, chunk_atoms 0 = all atoms,
+ *   persistent 0/1).
  * mtp_batch_neighbors: device pointers of the batch's CSR list (global atom indices). */
 typedef struct mtp_batch mtp_batch;
 int mtp_batch_create(mtp_model* m, int n_cfg, const int* atom_off, const double* pos, const int* species,
@@ -231,8 +251,9 @@ int mtp_batch_tune(mtp_batch* b, const char* cache_path, int* choice, void* stre
  *   Allocates nothing, never synchronizes; use_graph as for mtp_batch_run. */
 int mtp_batch_vjp(mtp_batch* b, const double* ebar, const double* fbar, double* d_linear, double* d_radial,
                   double* d_shift, int use_graph, void* stream);
-int mtp_batch_schedule(mtp_batch* b, int sorted, int chunk_atoms);
-int mtp_batch_sizes(const mtp_batch* b, int* n_atoms, long long* n_pairs, int* sorted, int* chunk_atoms);
+int mtp_batch_schedule(mtp_batch* b, int sorted, int chunk_atoms, int persistent);
+int mtp_batch_sizes(const mtp_batch* b, int* n_atoms, long long* n_pairs, int* sorted, int* chunk_atoms,
+                    int* persistent);
 int mtp_batch_neighbors(const mtp_batch* b, const int** off, const int** j, const int** shift,
                         const int** rev);
 void mtp_batch_destroy(mtp_batch* b);

@@ -25,7 +25,7 @@ MTP_GRADE_FP32SPLIT = 1
 
 EXPORTS = ("mtp_batch_create", "mtp_batch_run", "mtp_batch_vjp", "mtp_batch_tune", "mtp_batch_schedule", "mtp_batch_sizes",
            "mtp_batch_neighbors", "mtp_batch_destroy", "mtp_levels", "mtp_level_info", "mtp_profile", "mtp_profile_read", "mtp_profile_reset", "mtp_create", "mtp_destroy", "mtp_last_error", "mtp_sizes", "mtp_set_params",
-           "mtp_neighbors", "mtp_compute", "mtp_compute_static", "mtp_grade", "mtp_grade_config", "mtp_param_grad")
+           "mtp_neighbors", "mtp_compute", "mtp_compute_static", "mtp_grade", "mtp_grade_config", "mtp_param_grad", "mtp_maxvol")
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -112,12 +112,15 @@ def open_library(path: str):
     if hasattr(lib, "mtp_param_grad"):
         lib.mtp_param_grad.argtypes = [vp, ctypes.POINTER(MtpSystem), ctypes.POINTER(MtpNlist), d, vp, vp, vp,
                                        vp, vp]
+    lib.mtp_maxvol.argtypes = [vp, vp, i, i, vp, vp, d, i, ctypes.POINTER(i), c_double_p, ctypes.POINTER(i), vp]
+    lib.mtp_maxvol.restype = ctypes.c_int
     lib.mtp_batch_create.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, c_double_p, ctypes.POINTER(vp), vp]
     lib.mtp_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp]
     lib.mtp_batch_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i, vp]
     lib.mtp_batch_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i), vp]
-    lib.mtp_batch_schedule.argtypes = [vp, i, i]
-    lib.mtp_batch_sizes.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(ll), ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.mtp_batch_schedule.argtypes = [vp, i, i, i]
+    lib.mtp_batch_sizes.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(ll), ctypes.POINTER(i), ctypes.POINTER(i),
+                                    ctypes.POINTER(i)]
     lib.mtp_batch_neighbors.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                         ctypes.POINTER(vp)]
     lib.mtp_batch_destroy.argtypes = [vp]

@@ -233,6 +233,21 @@ class Potential:
                      (_lib.MTP_OK, _lib.MTP_GRADE_SELECT, _lib.MTP_GRADE_BREAK))
         return {"grade": g[0], "descriptor": desc, "status": code}
 
+    def maxvol(self, cand, active, ainv, tol=1e-3, max_swaps=100):
+        """MaxVol active-set update in place (device float64 tensors cand [m][n], active [n][n],
+        ainv [n][n]); returns the list of swaps (i, k, g)."""
+        n = int(active.shape[0])
+        m = int(cand.shape[0])
+        _dev(cand, torch.float64, (m, n), "cand")
+        _dev(active, torch.float64, (n, n), "active")
+        _dev(ainv, torch.float64, (n, n), "ainv")
+        sw = (ctypes.c_int * max(2 * max_swaps, 1))()
+        gr = (ctypes.c_double * max(max_swaps, 1))()
+        ns = ctypes.c_int()
+        check(self._lib.mtp_maxvol(self._h, _ptr(cand), m, n, _ptr(active), _ptr(ainv), float(tol), int(max_swaps),
+                                   sw, gr, ctypes.byref(ns), _stream()))
+        return [(sw[2 * t], sw[2 * t + 1], gr[t]) for t in range(ns.value)]
+
     def param_grad(self, pos, species, cell, ebar, fbar, nlist=None):
         sysc, n = self._system(pos, species, cell)
         dev = pos.device
@@ -287,18 +302,20 @@ class Batch:
             pass
 
     def sizes(self):
-        n, p, so, ch = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
-        check(self._lib.mtp_batch_sizes(self._h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(so), ctypes.byref(ch)))
-        return {"n_atoms": n.value, "n_pairs": p.value, "sorted": so.value, "chunk_atoms": ch.value}
+        n, p, so, ch, pe = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(self._lib.mtp_batch_sizes(self._h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(so), ctypes.byref(ch),
+                                        ctypes.byref(pe)))
+        return {"n_atoms": n.value, "n_pairs": p.value, "sorted": so.value, "chunk_atoms": ch.value,
+                "persistent": pe.value}
 
-    def schedule(self, sorted=False, chunk_atoms=0):
-        check(self._lib.mtp_batch_schedule(self._h, 1 if sorted else 0, int(chunk_atoms)))
+    def schedule(self, sorted=False, chunk_atoms=0, persistent=False):
+        check(self._lib.mtp_batch_schedule(self._h, 1 if sorted else 0, int(chunk_atoms), 1 if persistent else 0))
 
     def tune(self, cache_path=None):
-        choice = (ctypes.c_int * 2)()
+        choice = (ctypes.c_int * 3)()
         path = cache_path.encode() if cache_path else None
         check(self._lib.mtp_batch_tune(self._h, path, choice, _stream()))
-        return {"sorted": choice[0], "chunk_atoms": choice[1]}
+        return {"sorted": choice[0], "chunk_atoms": choice[1], "persistent": choice[2]}
 
     def vjp(self, ebar, fbar, use_graph=False):
         """sum_c ebar_c dE_c/dtheta + sum_i fbar_i . dF_i/dtheta for device cotangents ebar [n_cfg]

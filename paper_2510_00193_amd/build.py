@@ -122,7 +122,7 @@ def _compile(src, obj):
 
 def sources(levels):
     out = [os.path.join(CSRC, f) for f in ("mtp_api.cpp", "mtp_batch.cpp", "mtp_nbr.hip", "mtp_common.hip",
-                                           "mtp_grade.hip", "mtp_static.hip")]
+                                           "mtp_grade.hip", "mtp_static.hip", "mtp_maxvol.hip")]
     for lv in levels:
         out += [os.path.join(GEN, name) for name, _ in level_units(lv)]
     return out

@@ -378,6 +378,8 @@ SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist
   a.nsp = m->nsp;
   a.nmu = m->ops.nmu;
   a.ncheb = m->ncheb;
+  a.queue = nullptr;
+  a.pgrid = 0;
   return a;
 }
 

@@ -42,8 +42,10 @@ struct mtp_batch {
   // workspace
   DevBuf eatom, watom, g, fown, forces, energy, virial, mom, cbar, mbar, mdot, cbard, mbard, xout, dxi_part,
       cpart, wpart, ebar_cfg, fbar, parts, zeros;
+  DevBuf queue;                    // tile counters of the persistent pair-kernel launches
+  int pgrid = 0;                   // workgroups of a persistent launch
   // schedule
-  int sorted = 0, chunk = 0;
+  int sorted = 0, chunk = 0, persistent = 0;
   // graph
   hipStream_t gs = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -100,9 +102,26 @@ static int reserve_run(mtp_batch* b) {
   return MTP_OK;
 }
 
-static int set_schedule(mtp_batch* b, int sorted, int chunk) {
+// Pair-kernel launches of one run (the queue counters a persistent schedule needs).
+static long pair_launches(const mtp_batch* b) {
+  const LevelOps& L = b->m->ops;
+  const long ld = chunk_of(b);
+  const long nchunks = ((long)b->n + ld - 1) / ld;
+  return nchunks * (3L * L.ngroup + L.adj.ntgroup + L.adj.nagroup) + 1;
+}
+
+static int set_schedule(mtp_batch* b, int sorted, int chunk, int persistent) {
   b->sorted = sorted ? 1 : 0;
   b->chunk = chunk > 0 ? std::min(chunk, b->n) : b->n;
+  b->persistent = persistent ? 1 : 0;
+  if (b->persistent) {
+    // one workgroup per SIMD: the lane-per-atom pair kernels run one wave per SIMD
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    b->pgrid = 4 * ncu;
+    int rc = b->queue.reserve((size_t)pair_launches(b) * sizeof(int));
+    if (rc) return rc;
+  }
   std::vector<int> perm(b->n);
   std::iota(perm.begin(), perm.end(), 0);
   if (b->sorted) {
@@ -152,6 +171,14 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
   a.nsp = m->nsp;
   a.nmu = L.nmu;
   a.ncheb = m->ncheb;
+  a.queue = nullptr;
+  a.pgrid = b->pgrid;
+  // persistent schedule: one zeroed tile counter per pair-kernel launch (a kernel, not a memset,
+  // so that the sequence can be captured into a graph)
+  int* qbase = b->persistent ? (int*)b->queue.p : nullptr;
+  int qslot = 0;
+  if (qbase) launch_fill_int(qbase, pair_launches(b), 0, s);
+  auto q = [&]() { return qbase ? qbase + qslot++ : nullptr; };
   double* ea = (double*)b->eatom.p;
   double* wa = (double*)b->watom.p;
   double* g = (double*)b->g.p;
@@ -162,6 +189,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     const int cn = (int)std::min(ld, (long)n - i0);
     for (int gi = 0; gi < L.ngroup; ++gi) {
       ProfScope ps(&m->prof, P_MOMENTS, s);
+      a.queue = q();
       K.moments(gi, a, (int)i0, cn, b->mom.p, ld, s);
     }
     {
@@ -175,6 +203,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     }
     for (int gi = 0; gi < L.ngroup; ++gi) {
       ProfScope ps(&m->prof, P_BACKWARD, s);
+      a.queue = q();
       K.backward(gi, a, (int)i0, cn, b->mbar.p, ld, g, gi > 0, wpart + 6 * blk, wa, (double*)b->fown.p, s);
     }
     blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
@@ -218,6 +247,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     if (ld < n) {  // the forward state of this chunk was overwritten by later chunks
       for (int gi = 0; gi < L.ngroup; ++gi) {
         ProfScope ps(&m->prof, P_MOMENTS, s);
+        a.queue = q();
         K.moments(gi, a, (int)i0, cn, b->mom.p, ld, s);
       }
       {
@@ -232,6 +262,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     }
     for (int gi = 0; gi < L.adj.ntgroup; ++gi) {
       ProfScope ps(&m->prof, P_TANGENT, s);
+      a.queue = q();
       L.adj.tan_moments(gi, a, fbar, (int)i0, cn, (double*)b->mdot.p, ld, s);
     }
     {
@@ -246,6 +277,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
     }
     for (int gi = 0; gi < L.adj.nagroup; ++gi) {
       ProfScope ps(&m->prof, P_ADJ_PAIRS, s);
+      a.queue = q();
       L.adj.adj_pairs(gi, a, fbar, (int)i0, cn, (const double*)b->mbar.p, (const double*)b->mbard.p, ld, 0.0,
                   cpart + part * KR, s);
       part += cblk;
@@ -342,7 +374,7 @@ int mtp_batch_create(mtp_model* m, int n_cfg, const int* atom_off, const double*
     delete b;
     return mtp_fail(MTP_ERR_HIP, "reading neighbour offsets failed");
   }
-  if ((rc = set_schedule(b, 0, 0))) {
+  if ((rc = set_schedule(b, 0, 0, 0))) {
     delete b;
     return rc;
   }
@@ -352,12 +384,14 @@ int mtp_batch_create(mtp_model* m, int n_cfg, const int* atom_off, const double*
 
 void mtp_batch_destroy(mtp_batch* b) { delete b; }
 
-int mtp_batch_sizes(const mtp_batch* b, int* n_atoms, long long* n_pairs, int* sorted, int* chunk_atoms) {
+int mtp_batch_sizes(const mtp_batch* b, int* n_atoms, long long* n_pairs, int* sorted, int* chunk_atoms,
+                    int* persistent) {
   if (!b) return mtp_fail(MTP_ERR_ARG, "null batch");
   if (n_atoms) *n_atoms = b->n;
   if (n_pairs) *n_pairs = b->npairs;
   if (sorted) *sorted = b->sorted;
   if (chunk_atoms) *chunk_atoms = (int)chunk_of(b);
+  if (persistent) *persistent = b->persistent;
   return MTP_OK;
 }
 
@@ -370,9 +404,9 @@ int mtp_batch_neighbors(const mtp_batch* b, const int** off, const int** j, cons
   return MTP_OK;
 }
 
-int mtp_batch_schedule(mtp_batch* b, int sorted, int chunk_atoms) {
+int mtp_batch_schedule(mtp_batch* b, int sorted, int chunk_atoms, int persistent) {
   if (!b || chunk_atoms < 0) return mtp_fail(MTP_ERR_ARG, "null batch or negative chunk");
-  return set_schedule(b, sorted, chunk_atoms);
+  return set_schedule(b, sorted, chunk_atoms, persistent);
 }
 
 int mtp_batch_run(mtp_batch* b, const double* e_target, const double* f_target, double* energy, double* forces,
@@ -456,27 +490,34 @@ int mtp_batch_tune(mtp_batch* b, const char* cache_path, int* choice, void* stre
   const int bucket = b->n < 4096 ? 4096 : b->n < 65536 ? 65536 : b->n < 1048576 ? 1048576 : 1 << 30;
   char key[160];
   snprintf(key, sizeof(key), "gfx950-L%d-sp%d-q%d-n%d", m->ops.level, m->nsp, m->ncheb, bucket);
+  auto report = [&]() {
+    if (choice) {
+      choice[0] = b->sorted;
+      choice[1] = (int)chunk_of(b);
+      choice[2] = b->persistent;
+    }
+  };
   if (cache_path) {
     FILE* fh = fopen(cache_path, "r");
     if (fh) {
-      char k[160];
-      int so, ch;
-      while (fscanf(fh, "%159s %d %d", k, &so, &ch) == 3) {
-        if (strcmp(k, key) == 0) {
+      char line[256];
+      while (fgets(line, sizeof(line), fh)) {
+        char k[160];
+        int so = 0, ch = 0, pe = 0;
+        if (sscanf(line, "%159s %d %d %d", k, &so, &ch, &pe) == 4 && strcmp(k, key) == 0) {
           fclose(fh);
-          int rc = set_schedule(b, so, ch > 0 ? ch : 0);
-          if (!rc && choice) {
-            choice[0] = b->sorted;
-            choice[1] = (int)chunk_of(b);
-          }
+          int rc = set_schedule(b, so, ch > 0 ? ch : 0, pe);
+          if (!rc) report();
           return rc;
         }
       }
       fclose(fh);
     }
   }
+  // schedules: atom order (natural / sorted by neighbour count, longest rows first), chunk of
+  // atoms per pass, and static grids or persistent pair kernels pulling tiles from a queue
   std::vector<int> chunks = {0, 262144, 65536};
-  int best_sorted = 0, best_chunk = 0;
+  int best_sorted = 0, best_chunk = 0, best_pers = 0;
   float best_ms = -1.f;
   int rc;
   if ((rc = b->zeros.reserve(std::max<long>(3L * b->n, b->ncfg) * 8))) return rc;
@@ -490,39 +531,39 @@ int mtp_batch_tune(mtp_batch* b, const char* cache_path, int* choice, void* stre
   for (int so = 0; so < 2; ++so) {
     for (int ch : chunks) {
       if (ch > 0 && ch >= b->n) continue;
-      if ((rc = set_schedule(b, so, ch))) return rc;
-      const double* z = (const double*)b->zeros.p;
-      run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p,
-               (double*)ds.p, s);
-      HIP_TRY(hipEventRecord(e0, s));
-      for (int r = 0; r < 2; ++r)
+      for (int pe = 0; pe < 2; ++pe) {
+        if ((rc = set_schedule(b, so, ch, pe))) return rc;
+        const double* z = (const double*)b->zeros.p;
         run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p,
-               (double*)ds.p, s);
-      HIP_TRY(hipEventRecord(e1, s));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (best_ms < 0.f || ms < best_ms) {
-        best_ms = ms;
-        best_sorted = so;
-        best_chunk = ch;
+                 (double*)ds.p, s);
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 2; ++r)
+          run_impl(b, z, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)dl.p, (double*)dr.p,
+                   (double*)ds.p, s);
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best_sorted = so;
+          best_chunk = ch;
+          best_pers = pe;
+        }
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if ((rc = set_schedule(b, best_sorted, best_chunk))) return rc;
+  if ((rc = set_schedule(b, best_sorted, best_chunk, best_pers))) return rc;
   if (cache_path) {
     FILE* fh = fopen(cache_path, "a");
     if (fh) {
-      fprintf(fh, "%s %d %d\n", key, best_sorted, best_chunk);
+      fprintf(fh, "%s %d %d %d\n", key, best_sorted, best_chunk, best_pers);
       fclose(fh);
     }
   }
-  if (choice) {
-    choice[0] = b->sorted;
-    choice[1] = (int)chunk_of(b);
-  }
+  report();
   return MTP_OK;
 }
 

@@ -28,6 +28,11 @@ struct SysArgs {
   const int* pfirst;      // [N][nsp] first pair of each neighbour species, -1 if none
   double sa, sb, rcut;    // u = sa r + sb
   int nsp, nmu, ncheb;
+  // persistent launches of the pair kernels: a device counter from which workgroups pull their
+  // 64-atom tiles (zeroed before the launch), and the number of workgroups; null for a grid of
+  // one workgroup per tile
+  int* queue;
+  int pgrid;
 };
 
 // Energy/force chain of one level in one arithmetic type (per-atom buffers m, cbar, mbar are

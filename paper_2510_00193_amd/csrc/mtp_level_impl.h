@@ -8,6 +8,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "mtp_device.h"
@@ -16,6 +17,37 @@
 namespace mtp {
 
 constexpr int kLaneBlock = 64;   // one wave per workgroup for the lane-per-atom kernels
+
+// Tiles of kLaneBlock atoms a workgroup of a pair kernel processes: its own block of the grid
+// (PERSIST false: the loop body runs once), or, for a persistent launch, tiles pulled from the
+// device counter a.queue until none is left, so that workgroups that finish early take the
+// remaining tiles.  Every tile writes its own outputs (per-tile partials included), so the
+// result does not depend on which workgroup takes which tile.
+template <bool PERSIST>
+struct TileLoop {
+  int nblocks;
+  int* slot;  // LDS word that broadcasts a pulled tile to the workgroup
+  __device__ __forceinline__ int pull(int* q) const {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(q, 1);
+    __syncthreads();
+    return *slot;
+  }
+  __device__ __forceinline__ int first(const SysArgs& a) const {
+    if constexpr (PERSIST) return pull(a.queue);
+    else return xcd_logical_block(blockIdx.x, gridDim.x);
+  }
+  __device__ __forceinline__ int next(const SysArgs& a) const {
+    if constexpr (PERSIST) return pull(a.queue);
+    else return nblocks;
+  }
+};
+#define MTP_FOR_TILES(a, n, b)                                                         \
+  __shared__ int tile_slot_;                                                           \
+  const TileLoop<PERSIST> tiles_{((n) + kLaneBlock - 1) / kLaneBlock, &tile_slot_};    \
+  for (int b = tiles_.first(a); b < tiles_.nblocks; b = tiles_.next(a))
+
+inline int pair_grid(const SysArgs& a, int nb) { return a.queue ? std::max(1, std::min(nb, a.pgrid)) : nb; }
 
 // Accessor of a moment vector held in global memory in [entry][atom] layout.
 template <class R>
@@ -115,14 +147,14 @@ __device__ __forceinline__ void cell_of(const SysArgs& a, int i, double* H) {
   }
 }
 
-template <class L, int G, class R, bool BATCH, int NC>
+template <class L, int G, class R, bool BATCH, int NC, bool PERSIST = false>
 __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
                                                         R* __restrict__ mout, long ld) {
   __shared__ R csh[kMaxRadial];
   stage_radial(a, csh);
-  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  MTP_FOR_TILES(a, n, b) {
   const int li = b * kLaneBlock + threadIdx.x;
-  if (li >= n) return;
+  if (li >= n) continue;
   const int i = sweep_atom<BATCH>(a, i0 + li);
   double H[9];
   cell_of<BATCH>(a, i, H);
@@ -140,6 +172,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
   });
 #pragma unroll
   for (int e = 0; e < NG; ++e) mout[(long)(LO + e) * ld + li] = m[e];
+  }
 }
 
 // ---------------------------------------------------------------------------- program forward
@@ -231,7 +264,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_program(const R* __restrict__ mo
 // ---------------------------------------------------------------------------- backward pairs
 // g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials;
 // fown[i] (+)= sum of the atom's own g over its row (the first half of its force), when given.
-template <class L, int G, class R, bool BATCH, int NC>
+template <class L, int G, class R, bool BATCH, int NC, bool PERSIST = false>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
                                                          const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
@@ -241,7 +274,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
   __shared__ R csh[kMaxRadial];
   __shared__ double red[kLaneBlock];
   stage_radial(a, csh);
-  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  MTP_FOR_TILES(a, n, b) {
   const int li = b * kLaneBlock + threadIdx.x;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   double w[6] = {0, 0, 0, 0, 0, 0};
@@ -301,20 +334,21 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     const double s = block_sum<kLaneBlock>(w[k], red);
     if (threadIdx.x == 0) wpart[6L * b + k] = accumulate ? wpart[6L * b + k] + s : s;
   }
+  }
 }
 
 // ---------------------------------------------------------------------------- parameter adjoint
 // Tangent of the moments along delta_ij = fbar_j - fbar_i (the direction in which the
 // force-weighted loss term differentiates the energy).
-template <class L, int G>
+template <class L, int G, bool PERSIST = false>
 __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const double* __restrict__ fbar,
                                                             int i0, int n, double* __restrict__ mdot,
                                                             long ld) {
   __shared__ double csh[kMaxRadial];
   stage_radial(a, csh);
-  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  MTP_FOR_TILES(a, n, b) {
   const int li = b * kLaneBlock + threadIdx.x;
-  if (li >= n) return;
+  if (li >= n) continue;
   const int i = atom_at(a, i0 + li);
   double H[9];
   load_cell(a, i, H);
@@ -334,6 +368,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
   });
 #pragma unroll
   for (int e = 0; e < NG; ++e) mdot[(long)(LO + e) * ld + li] = md[e];
+  }
 }
 
 // Tangents of contractions and basis: out[alpha] = ebar B_alpha - dB_alpha, and dCbar.
@@ -407,13 +442,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 // [AMU_LO, AMU_HI] stay in registers; the partial rows of the other mu values are written as
 // zeros. NC is the compile-time Chebyshev count (0: runtime count up to kMaxCheb); every index
 // into the accumulators is a compile-time constant.
-template <class L, int G, int NC>
+template <class L, int G, int NC, bool PERSIST = false>
 __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const double* __restrict__ fbar,
                                                           int i0, int n,
                                                           const double* __restrict__ mbar,
                                                           const double* __restrict__ mbard, long ld,
                                                           double ebar, double* __restrict__ cpart) {
-  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+  const double ebar0 = ebar;
+  MTP_FOR_TILES(a, n, b) {
+  ebar = ebar0;
   const int li = b * kLaneBlock + threadIdx.x;
   constexpr int LO = L::AGROUP_LO[G], HI = L::AGROUP_HI[G], NG = HI - LO;
   constexpr int NMU = L::NMU, MLO = L::AMU_LO[G], MHI = L::AMU_HI[G], NM = MHI - MLO + 1;
@@ -514,20 +551,29 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
         }
     }
   }
+  }
 }
 
 // ---------------------------------------------------------------------------- launchers
 // The pair kernels come in Chebyshev-count specialisations for the common sizes 8 and 10 and a
 // runtime-count form for the rest.
+template <class L, int G, class R, bool BATCH, bool PERSIST>
+void launch_moments_gp(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
+  const int nb = pair_grid(a, (n + kLaneBlock - 1) / kLaneBlock);
+  if (a.ncheb == 8)
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 8, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  else if (a.ncheb == 10)
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 10, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  else
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 0, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+}
+// persistent variants exist for batches only (a single system uses one grid of its tiles)
 template <class L, int G, class R, bool BATCH>
 void launch_moments_g(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
-  const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  if (a.ncheb == 8)
-    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
-  else if (a.ncheb == 10)
-    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
-  else
-    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+  if constexpr (BATCH) {
+    if (a.queue) return launch_moments_gp<L, G, R, BATCH, true>(a, i0, n, m, ld, s);
+  }
+  launch_moments_gp<L, G, R, BATCH, false>(a, i0, n, m, ld, s);
 }
 template <class L, int G, class R>
 void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipStream_t s) {
@@ -535,19 +581,27 @@ void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipSt
   hipLaunchKernelGGL((k_program_rev<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, n,
                      (const R*)cb, (R*)mb);
 }
+template <class L, int G, class R, bool BATCH, bool PERSIST>
+void launch_backward_gp(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
+                        int acc, double* wpart, double* watom, double* fown, hipStream_t s) {
+  const int nb = pair_grid(a, (n + kLaneBlock - 1) / kLaneBlock);
+  if (a.ncheb == 8)
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 8, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+                       (const R*)mb, ld, g, acc, wpart, watom, fown);
+  else if (a.ncheb == 10)
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 10, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+                       (const R*)mb, ld, g, acc, wpart, watom, fown);
+  else
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 0, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+                       (const R*)mb, ld, g, acc, wpart, watom, fown);
+}
 template <class L, int G, class R, bool BATCH>
 void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                        int acc, double* wpart, double* watom, double* fown, hipStream_t s) {
-  const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-  if (a.ncheb == 8)
-    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
-                       (const R*)mb, ld, g, acc, wpart, watom, fown);
-  else if (a.ncheb == 10)
-    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
-                       (const R*)mb, ld, g, acc, wpart, watom, fown);
-  else
-    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
-                       (const R*)mb, ld, g, acc, wpart, watom, fown);
+  if constexpr (BATCH) {
+    if (a.queue) return launch_backward_gp<L, G, R, BATCH, true>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
+  }
+  launch_backward_gp<L, G, R, BATCH, false>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
 }
 
 template <class L, class R, bool BATCH, size_t... Gs>
@@ -607,8 +661,11 @@ struct AdjImpl {
   template <int G>
   static void tan_moments_g(const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
                             hipStream_t s) {
-    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-    hipLaunchKernelGGL((k_tan_moments<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, md, ld);
+    const int nb = pair_grid(a, (n + kLaneBlock - 1) / kLaneBlock);
+    if (a.queue)
+      hipLaunchKernelGGL((k_tan_moments<L, G, true>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, md, ld);
+    else
+      hipLaunchKernelGGL((k_tan_moments<L, G, false>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, md, ld);
   }
   template <size_t... Gs>
   static void tan_moments_d(int g, const SysArgs& a, const double* fbar, int i0, int n, double* md, long ld,
@@ -634,15 +691,21 @@ struct AdjImpl {
   template <int G>
   static void adj_pairs_g(const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
                           const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
-    const int nb = (n + kLaneBlock - 1) / kLaneBlock;
+    const int nb = pair_grid(a, (n + kLaneBlock - 1) / kLaneBlock);
+    if (a.queue) adj_pairs_gp<G, true>(nb, a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s);
+    else adj_pairs_gp<G, false>(nb, a, fbar, i0, n, mb, mbd, ld, ebar, cpart, s);
+  }
+  template <int G, bool P>
+  static void adj_pairs_gp(int nb, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
+                           const double* mbd, long ld, double ebar, double* cpart, hipStream_t s) {
     if (a.ncheb == 8)
-      hipLaunchKernelGGL((k_adj_pairs<L, G, 8>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+      hipLaunchKernelGGL((k_adj_pairs<L, G, 8, P>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
                          ebar, cpart);
     else if (a.ncheb == 10)
-      hipLaunchKernelGGL((k_adj_pairs<L, G, 10>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+      hipLaunchKernelGGL((k_adj_pairs<L, G, 10, P>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
                          ebar, cpart);
     else
-      hipLaunchKernelGGL((k_adj_pairs<L, G, 0>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
+      hipLaunchKernelGGL((k_adj_pairs<L, G, 0, P>), dim3(nb), dim3(kLaneBlock), 0, s, a, fbar, i0, n, mb, mbd, ld,
                          ebar, cpart);
   }
   template <size_t... Gs>

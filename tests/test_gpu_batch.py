@@ -92,10 +92,19 @@ def test_batch_graph_replay_schedules_and_parameter_update():
         _ = (dpos * 2.0).sum().item()
         for k in ref:
             assert torch.equal(out[k], ref[k]), k
-    for sorted_, chunk in ((True, 0), (False, 64), (True, 50)):
-        b.schedule(sorted=sorted_, chunk_atoms=chunk)
+    for sorted_, chunk, pers in ((True, 0, False), (False, 64, False), (True, 50, False), (False, 0, True),
+                                 (True, 64, True)):
+        b.schedule(sorted=sorted_, chunk_atoms=chunk, persistent=pers)
         o = b.run(b.outputs(), e0, f0)
         torch.cuda.synchronize()
+        if pers:  # persistent pair kernels inside a captured graph, replayed with eager work between
+            og = b.outputs()
+            for _ in range(3):
+                b.run(og, e0, f0, use_graph=True)
+                torch.cuda.synchronize()
+                _ = (dpos * 2.0).sum().item()
+                for k in ref:
+                    assert torch.equal(og[k], o[k]), k
         assert torch.equal(o["energy"], ref["energy"])
         assert torch.equal(o["forces"], ref["forces"])
         for k in ("loss", "virial", "d_linear", "d_radial", "d_shift"):

@@ -1,0 +1,66 @@
+"""GPU parity of the MaxVol active-set update (mtp_maxvol) against the oracle: the same swap
+sequence, the same active and candidate rows afterwards, the inverse kept consistent."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import rel_err, small_lattice
+from oracle import maxvol as omv
+from oracle import mtp as om
+
+pytestmark = pytest.mark.gpu
+
+
+def _pot(p):
+    from paper_2510_00193_amd import Potential
+    return Potential.from_params(p)
+
+
+def _run(pot, active, cand, tol, max_swaps, label):
+    print(f"[{label}] n={active.shape[0]} m={cand.shape[0]} tol={tol}", flush=True)
+    A = torch.as_tensor(active.copy(), device="cuda")
+    C = torch.as_tensor(cand.copy(), device="cuda")
+    Ai = torch.as_tensor(np.linalg.inv(active), device="cuda")
+    swaps = pot.maxvol(C, A, Ai, tol=tol, max_swaps=max_swaps)
+    torch.cuda.synchronize()
+    a1, c1, ref = omv.maxvol_update(active, cand, tol=tol, max_swaps=max_swaps)
+    assert [(i, k) for i, k, _ in swaps] == [(i, k) for i, k, _ in ref]
+    assert np.allclose([g for *_, g in swaps], [g for *_, g in ref], rtol=1e-9, atol=0)
+    np.testing.assert_array_equal(A.cpu().numpy(), a1)
+    np.testing.assert_array_equal(C.cpu().numpy(), c1)
+    assert rel_err(Ai.cpu().numpy(), np.linalg.inv(a1)) < 1e-9
+    return swaps
+
+
+def test_maxvol_random_matrices():
+    s, p = small_lattice(91, (2, 2, 2), 3.16, 0.05, 6, 1)
+    pot = _pot(p)
+    rng = np.random.default_rng(7)
+    for n, m, tol in ((5, 64, 1e-3), (17, 300, 1e-2), (40, 1000, 1e-3), (1, 9, 0.0)):
+        active = np.eye(n) + 0.3 * rng.normal(size=(n, n))
+        cand = rng.normal(size=(m, n))
+        swaps = _run(pot, active, cand, tol, 200, f"random n{n} m{m}")
+        assert len(swaps) > 0
+
+
+def test_maxvol_on_basis_vectors_of_a_lattice():
+    """Candidates are the per-atom basis vectors B_i of a jittered lattice (the neighbourhood-mode
+    active-learning setting), the active set starts from the first n atoms."""
+    s, p = small_lattice(92, (3, 3, 3), 3.16, 0.2, 10, 1)
+    model = om.Model.from_params(p)
+    b = om.energy_forces_virial(model, s)["B"].detach().numpy()
+    n = b.shape[1]
+    rng = np.random.default_rng(8)
+    active = b[:n] + 1e-3 * rng.normal(size=(n, n))  # well conditioned start
+    cand = b[n:]
+    _run(_pot(p), active, cand, 1e-3, 100, "bcc 3^3 L10 basis vectors")
+
+
+def test_maxvol_stops_at_once_when_grades_are_below_one():
+    s, p = small_lattice(93, (2, 2, 2), 3.16, 0.05, 6, 1)
+    pot = _pot(p)
+    rng = np.random.default_rng(9)
+    n, m = 6, 50
+    active = np.eye(n) + 0.2 * rng.normal(size=(n, n))
+    cand = rng.uniform(-0.4, 0.4, size=(m, n)) @ active
+    assert _run(pot, active, cand, 1e-3, 10, "below one") == []

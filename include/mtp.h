@@ -75,6 +75,12 @@ typedef struct {
                             about 2 KB of workspace per atom at level 16) */
   double grade_select;   /* grade_max above this returns MTP_GRADE_SELECT; <= 0 disables */
   double grade_break;    /* grade_max above this returns MTP_GRADE_BREAK; <= 0 disables */
+  int lanes_per_atom;    /* lanes that share one atom's neighbour loop in the binary64 pair
+                            kernels (moments, pair gradients) of a single system: 1, 2, 4 or 8,
+                            or 0 = chosen from the system size so that the waves cover the
+                            GPU's SIMDs (small systems; cf. the paper's block-parallel variant
+                            for small atom counts, Section 2.1).  The binary32 form and batches
+                            use one lane per atom. */
 } mtp_params;
 
 typedef struct {

@@ -44,6 +44,7 @@ class MtpParams(ctypes.Structure):
         ("chunk_atoms", ctypes.c_int),
         ("grade_select", ctypes.c_double),
         ("grade_break", ctypes.c_double),
+        ("lanes_per_atom", ctypes.c_int),
     ]
 
 

@@ -87,7 +87,7 @@ class Potential:
     """One MTP model on the current GPU."""
 
     def __init__(self, level, n_species, n_cheb, r_min, r_cut, radial, linear, shift, precision="fp64",
-                 chunk_atoms=0, grade_select=0.0, grade_break=0.0):
+                 chunk_atoms=0, grade_select=0.0, grade_break=0.0, lanes_per_atom=0):
         self._lib = _lib.load()
         self._h = None
         radial = np.ascontiguousarray(radial, dtype=np.float64)
@@ -97,7 +97,7 @@ class Potential:
         p = MtpParams(int(level), int(n_species), int(n_cheb), float(r_min), float(r_cut),
                       radial.ctypes.data_as(_lib.c_double_p), linear.ctypes.data_as(_lib.c_double_p),
                       shift.ctypes.data_as(_lib.c_double_p), prec, int(chunk_atoms), float(grade_select),
-                      float(grade_break))
+                      float(grade_break), int(lanes_per_atom))
         h = ctypes.c_void_p()
         check(self._lib.mtp_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h

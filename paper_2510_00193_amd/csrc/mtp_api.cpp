@@ -188,6 +188,9 @@ int mtp_create(const mtp_params* p, mtp_model** out) {
   if (p->precision != MTP_FP64 && p->precision != MTP_FP32_MOMENTS)
     return mtp_fail(MTP_ERR_ARG, "unknown precision");
   if (p->chunk_atoms < 0) return mtp_fail(MTP_ERR_ARG, "chunk_atoms < 0");
+  if (p->lanes_per_atom != 0 && p->lanes_per_atom != 1 && p->lanes_per_atom != 2 && p->lanes_per_atom != 4 &&
+      p->lanes_per_atom != 8)
+    return mtp_fail(MTP_ERR_ARG, "lanes_per_atom must be 0, 1, 2, 4 or 8");
   if (p->precision == MTP_FP32_MOMENTS && !ops.chain[1].moments)
     return mtp_fail(MTP_ERR_LEVEL, "the binary32 form is not compiled for level " + std::to_string(p->level));
   const long nrad = (long)p->n_species * p->n_species * ops.nmu * p->n_cheb;
@@ -202,6 +205,11 @@ int mtp_create(const mtp_params* p, mtp_model** out) {
   m->chunk = p->chunk_atoms > 0 ? p->chunk_atoms : kDefaultChunk;
   m->grade_select = p->grade_select;
   m->grade_break = p->grade_break;
+  m->split = p->lanes_per_atom;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  }
   m->nrad = nrad;
   int rc = MTP_OK;
   if ((rc = m->radial.reserve(nrad * sizeof(double))) || (rc = m->linear.reserve(ops.nalpha * sizeof(double))) ||
@@ -380,11 +388,25 @@ SysArgs make_sys_args(const mtp_model* m, const mtp_system* sys, const mtp_nlist
   a.ncheb = m->ncheb;
   a.queue = nullptr;
   a.pgrid = 0;
+  a.split = pair_split(m, sys->n_atoms);
   return a;
 }
 
-long chain_wpart_blocks(int n, int chunk) {
-  return ((long)n + kLaneBlockHost - 1) / kLaneBlockHost + (n / std::max(chunk, 1) + 1);
+// Small systems leave SIMDs idle with one lane per atom (a wave per 64 atoms, one wave per
+// SIMD at these register counts): the lanes per atom double while the waves still fit on the
+// SIMDs (4 per compute unit) at once.
+int pair_split(const mtp_model* m, int n) {
+  if (m->precision != MTP_FP64) return 1;
+  if (m->split > 0) return m->split;
+  int k = 1;
+  while (k < 8 && (long)n * 2 * k <= (long)kLaneBlockHost * 4 * m->ncu) k *= 2;
+  return k;
+}
+
+long pair_blocks(int n, int split) { return ((long)n * split + kLaneBlockHost - 1) / kLaneBlockHost; }
+
+long chain_wpart_blocks(int n, int chunk, int split) {
+  return pair_blocks(n, split) + (n / std::max(chunk, 1) + 1);
 }
 
 int chain_work_reserve(mtp_model* m, int n, long long npairs, bool backward, ChainWork* w) {
@@ -402,7 +424,7 @@ int chain_work_reserve(mtp_model* m, int n, long long npairs, bool backward, Cha
     if ((rc = m->mbar.reserve((size_t)L.nmom * chunk * sizeof(double))) ||
         (rc = m->g.reserve((size_t)std::max<long long>(npairs, 1) * 3 * sizeof(double))) ||
         (rc = m->fown.reserve((size_t)std::max(n, 1) * 3 * sizeof(double))) ||
-        (rc = m->wpart.reserve((size_t)chain_wpart_blocks(n, chunk) * 6 * sizeof(double))))
+        (rc = m->wpart.reserve((size_t)chain_wpart_blocks(n, chunk, pair_split(m, n)) * 6 * sizeof(double))))
       return rc;
     w->mbar = m->mbar.p;
     w->g = (double*)m->g.p;
@@ -444,7 +466,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
         ProfScope ps(&m->prof, P_BACKWARD, s);
         K.backward(0, a, i0, cn, mbar, ld, w.g, 0, w.wpart + 6 * blk, nullptr, w.fown, s);
       }
-      blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
+      blk += pair_blocks(cn, a.split);
       continue;
     }
     {
@@ -462,7 +484,7 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
         ProfScope ps(&m->prof, P_BACKWARD, s);
         K.backward(g, a, i0, cn, mbar, ld, w.g, g > 0, w.wpart + 6 * blk, nullptr, w.fown, s);
       }
-      blk += (cn + kLaneBlockHost - 1) / kLaneBlockHost;
+      blk += pair_blocks(cn, a.split);
     }
   }
   w.wblocks = blk;

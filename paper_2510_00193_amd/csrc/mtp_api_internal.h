@@ -52,6 +52,7 @@ struct ProfScope {
 struct mtp_model {
   mtp::LevelOps ops;
   int nsp = 0, ncheb = 0, precision = 0, chunk = 0;
+  int split = 0, ncu = 256;  // lanes per atom (0 = by system size), compute units of the device
   long nrad = 0;
   double rmin = 0, rcut = 0, grade_select = 0, grade_break = 0;
   DevBuf radial, linear, shift;                        // coefficients (device)
@@ -83,8 +84,12 @@ struct ChainWork {
   int chunk = 1;
   long wblocks = 0;
 };
+// lanes per atom of the binary64 single-system pair kernels for a system of n atoms
+int pair_split(const mtp_model* m, int n);
+// workgroups of a pair kernel over n atoms with `split` lanes per atom (one virial partial each)
+long pair_blocks(int n, int split);
 // upper bound of the virial partials the chain writes for n atoms in chunks of `chunk`
-long chain_wpart_blocks(int n, int chunk);
+long chain_wpart_blocks(int n, int chunk, int split);
 // chain buffers from the model's grow-only workspace
 int chain_work_reserve(mtp_model* m, int n, long long npairs, bool backward, ChainWork* w);
 int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, double* e_atom,

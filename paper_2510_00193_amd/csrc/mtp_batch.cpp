@@ -173,6 +173,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
   a.ncheb = m->ncheb;
   a.queue = nullptr;
   a.pgrid = b->pgrid;
+  a.split = 1;
   // persistent schedule: one zeroed tile counter per pair-kernel launch (a kernel, not a memset,
   // so that the sequence can be captured into a graph)
   int* qbase = b->persistent ? (int*)b->queue.p : nullptr;

@@ -33,6 +33,9 @@ struct SysArgs {
   // one workgroup per tile
   int* queue;
   int pgrid;
+  // lanes per atom of the single-system pair kernels (1, 2, 4 or 8): with more than one, the
+  // lanes of an atom take every split-th pair of its row and combine their sums
+  int split;
 };
 
 // Energy/force chain of one level in one arithmetic type (per-atom buffers m, cbar, mbar are

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "mtp_device.h"
@@ -42,10 +43,34 @@ struct TileLoop {
     else return nblocks;
   }
 };
-#define MTP_FOR_TILES(a, n, b)                                                         \
-  __shared__ int tile_slot_;                                                           \
-  const TileLoop<PERSIST> tiles_{((n) + kLaneBlock - 1) / kLaneBlock, &tile_slot_};    \
+// K lanes per atom: a tile holds kLaneBlock / K atoms
+#define MTP_FOR_TILES_K(a, n, K, b)                                                                    \
+  __shared__ int tile_slot_;                                                                           \
+  const TileLoop<PERSIST> tiles_{(int)(((long)(n) * (K) + kLaneBlock - 1) / kLaneBlock), &tile_slot_}; \
   for (int b = tiles_.first(a); b < tiles_.nblocks; b = tiles_.next(a))
+#define MTP_FOR_TILES(a, n, b) MTP_FOR_TILES_K(a, n, 1, b)
+
+// Sum over the K consecutive lanes of an atom (K = 1, 2, 4, 8) by DPP lane exchanges inside
+// quads and half-rows; every lane of the group ends with the same value (each step adds two
+// equal partial sums in either order, which is exact commutativity).
+template <int CTRL>
+__device__ __forceinline__ double dpp_exchange(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_exchange(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int K, class R>
+__device__ __forceinline__ R group_sum(R v) {
+  static_assert(K == 1 || K == 2 || K == 4 || K == 8, "lanes per atom");
+  if constexpr (K >= 2) v += dpp_exchange<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  if constexpr (K >= 4) v += dpp_exchange<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  if constexpr (K >= 8) v += dpp_exchange<0x141>(v);  // row_half_mirror
+  return v;
+}
 
 inline int pair_grid(const SysArgs& a, int nb) { return a.queue ? std::max(1, std::min(nb, a.pgrid)) : nb; }
 
@@ -93,23 +118,24 @@ __device__ __forceinline__ void stage_radial(const SysArgs& a, R* sh) {
 // Walk the CSR row of atom i with software prefetch: the partner indices are loaded two pairs
 // ahead and the partner position/species one pair ahead, so the gather latency overlaps the
 // arithmetic of the current pair.  body(p, j, zj, dx, dy, dz, r) sees the exact displacement.
-template <class F>
-__device__ __forceinline__ void for_pairs(const SysArgs& a, int i, const double* H, double rix, double riy,
-                                          double riz, F&& body) {
-  const int p0 = a.off[i], p1 = a.off[i + 1];
+// With K lanes per atom, lane sub of the atom takes pairs sub, sub + K, sub + 2K, ... of the row.
+template <int K = 1, class F>
+__device__ __forceinline__ void for_pairs(const SysArgs& a, int i, int sub, const double* H, double rix,
+                                          double riy, double riz, F&& body) {
+  const int p0 = a.off[i] + sub, p1 = a.off[i + 1];
   if (p0 >= p1) return;
   int jA = a.nj[p0], shA = a.shift[p0];
   double xA = a.pos[3 * jA], yA = a.pos[3 * jA + 1], zA = a.pos[3 * jA + 2];
   int sA = a.species[jA];
   int jB = 0, shB = 0;
-  if (p0 + 1 < p1) {
-    jB = a.nj[p0 + 1];
-    shB = a.shift[p0 + 1];
+  if (p0 + K < p1) {
+    jB = a.nj[p0 + K];
+    shB = a.shift[p0 + K];
   }
-  for (int p = p0; p < p1; ++p) {
+  for (int p = p0; p < p1; p += K) {
     const int j = jA, sh = shA, sj = sA;
     const double xj = xA, yj = yA, zj = zA;
-    if (p + 1 < p1) {
+    if (p + K < p1) {
       xA = a.pos[3 * jB];
       yA = a.pos[3 * jB + 1];
       zA = a.pos[3 * jB + 2];
@@ -117,9 +143,9 @@ __device__ __forceinline__ void for_pairs(const SysArgs& a, int i, const double*
       jA = jB;
       shA = shB;
     }
-    if (p + 2 < p1) {
-      jB = a.nj[p + 2];
-      shB = a.shift[p + 2];
+    if (p + 2 * K < p1) {
+      jB = a.nj[p + 2 * K];
+      shB = a.shift[p + 2 * K];
     }
     int n1, n2, n3;
     unpack_shift(sh, n1, n2, n3);
@@ -147,13 +173,16 @@ __device__ __forceinline__ void cell_of(const SysArgs& a, int i, double* H) {
   }
 }
 
-template <class L, int G, class R, bool BATCH, int NC, bool PERSIST = false>
+// K lanes per atom (single systems): each accumulates every K-th pair of the row, the partial
+// moments are summed over the atom's lanes and its first lane writes them.
+template <class L, int G, class R, bool BATCH, int NC, bool PERSIST = false, int K = 1>
 __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n,
                                                         R* __restrict__ mout, long ld) {
+  static_assert(K == 1 || !BATCH, "batches take one lane per atom");
   __shared__ R csh[kMaxRadial];
   stage_radial(a, csh);
-  MTP_FOR_TILES(a, n, b) {
-  const int li = b * kLaneBlock + threadIdx.x;
+  MTP_FOR_TILES_K(a, n, K, b) {
+  const int li = b * (kLaneBlock / K) + (int)threadIdx.x / K, sub = (int)threadIdx.x % K;
   if (li >= n) continue;
   const int i = sweep_atom<BATCH>(a, i0 + li);
   double H[9];
@@ -165,13 +194,19 @@ __global__ __launch_bounds__(kLaneBlock) void k_moments(SysArgs a, int i0, int n
   const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
   const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
-  for_pairs(a, i, H, rix, riy, riz, [&](int, int, int zj, double dx, double dy, double dz, double r) {
+  for_pairs<K>(a, i, sub, H, rix, riy, riz, [&](int, int, int zj, double dx, double dy, double dz, double r) {
     R f[L::NMU];
     radial_values<R, L::NMU, NC>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f);
     L::template acc_moments<G>(m, f, (R)dx, (R)dy, (R)dz);
   });
+  if constexpr (K > 1) {
 #pragma unroll
-  for (int e = 0; e < NG; ++e) mout[(long)(LO + e) * ld + li] = m[e];
+    for (int e = 0; e < NG; ++e) m[e] = group_sum<K>(m[e]);
+  }
+  if (sub == 0) {
+#pragma unroll
+    for (int e = 0; e < NG; ++e) mout[(long)(LO + e) * ld + li] = m[e];
+  }
   }
 }
 
@@ -264,18 +299,21 @@ __global__ __launch_bounds__(kLaneBlock) void k_program(const R* __restrict__ mo
 // ---------------------------------------------------------------------------- backward pairs
 // g[p] (+)= dE_i/dd_ij restricted to the entries of group G; per-workgroup virial partials;
 // fown[i] (+)= sum of the atom's own g over its row (the first half of its force), when given.
-template <class L, int G, class R, bool BATCH, int NC, bool PERSIST = false>
+// K lanes per atom (single systems): each takes every K-th pair of the row; the own sums are
+// combined over the atom's lanes, the virial partial over the workgroup as before.
+template <class L, int G, class R, bool BATCH, int NC, bool PERSIST = false, int K = 1>
 __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int n,
                                                          const R* __restrict__ mbar, long ld,
                                                          double* __restrict__ g, int accumulate,
                                                          double* __restrict__ wpart,
                                                          double* __restrict__ watom,
                                                          double* __restrict__ fown) {
+  static_assert(K == 1 || !BATCH, "batches take one lane per atom");
   __shared__ R csh[kMaxRadial];
   __shared__ double red[kLaneBlock];
   stage_radial(a, csh);
-  MTP_FOR_TILES(a, n, b) {
-  const int li = b * kLaneBlock + threadIdx.x;
+  MTP_FOR_TILES_K(a, n, K, b) {
+  const int li = b * (kLaneBlock / K) + (int)threadIdx.x / K, sub = (int)threadIdx.x % K;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
   double w[6] = {0, 0, 0, 0, 0, 0};
   double fo[3] = {0, 0, 0};  // sum of the atom's own pair gradients
@@ -290,7 +328,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
     const int zi = clamp_species(a.species[i], a.nsp);
     const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
-    for_pairs(a, i, H, rix, riy, riz, [&](int p, int, int zj, double dx, double dy, double dz, double r) {
+    for_pairs<K>(a, i, sub, H, rix, riy, riz, [&](int p, int, int zj, double dx, double dy, double dz, double r) {
       R f[L::NMU], fp[L::NMU];
       radial<R, L::NMU, NC>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f, fp);
       R rgx = R(0), rgy = R(0), rgz = R(0), ru = R(0);
@@ -322,7 +360,11 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
 #pragma unroll
       for (int k = 0; k < 6; ++k) watom[6L * i + k] = accumulate ? watom[6L * i + k] + w[k] : w[k];
     }
-    if (fown) {
+    if constexpr (K > 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) fo[k] = group_sum<K>(fo[k]);
+    }
+    if (fown && sub == 0) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) fown[3L * i + k] = accumulate ? fown[3L * i + k] + fo[k] : fo[k];
     }
@@ -359,7 +401,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_moments(SysArgs a, const dou
   const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
   const double fix = fbar[3 * i], fiy = fbar[3 * i + 1], fiz = fbar[3 * i + 2];
   const int zi = clamp_species(a.species[i], a.nsp);
-  for_pairs(a, i, H, rix, riy, riz, [&](int, int j, int zj, double dx, double dy, double dz, double r) {
+  for_pairs(a, i, 0, H, rix, riy, riz, [&](int, int j, int zj, double dx, double dy, double dz, double r) {
     double f[L::NMU], fp[L::NMU];
     radial<double, L::NMU>(r, a.sa, a.sb, a.rcut, csh + (zi * a.nsp + zj) * L::NMU * a.ncheb, a.ncheb, f, fp);
     const double ex = fbar[3 * j] - fix, ey = fbar[3 * j + 1] - fiy, ez = fbar[3 * j + 2] - fiz;
@@ -557,21 +599,28 @@ __global__ __launch_bounds__(kLaneBlock) void k_adj_pairs(SysArgs a, const doubl
 // ---------------------------------------------------------------------------- launchers
 // The pair kernels come in Chebyshev-count specialisations for the common sizes 8 and 10 and a
 // runtime-count form for the rest.
-template <class L, int G, class R, bool BATCH, bool PERSIST>
+inline int split_tiles(int n, int k) { return (int)(((long)n * k + kLaneBlock - 1) / kLaneBlock); }
+
+template <class L, int G, class R, bool BATCH, bool PERSIST, int K = 1>
 void launch_moments_gp(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
-  const int nb = pair_grid(a, (n + kLaneBlock - 1) / kLaneBlock);
+  const int nb = pair_grid(a, split_tiles(n, K));
   if (a.ncheb == 8)
-    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 8, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 8, PERSIST, K>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
   else if (a.ncheb == 10)
-    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 10, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 10, PERSIST, K>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
   else
-    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 0, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
+    hipLaunchKernelGGL((k_moments<L, G, R, BATCH, 0, PERSIST, K>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n, (R*)m, ld);
 }
-// persistent variants exist for batches only (a single system uses one grid of its tiles)
+// persistent variants exist for batches only (a single system uses one grid of its tiles);
+// split lanes for single systems in binary64 only
 template <class L, int G, class R, bool BATCH>
 void launch_moments_g(const SysArgs& a, int i0, int n, void* m, long ld, hipStream_t s) {
   if constexpr (BATCH) {
     if (a.queue) return launch_moments_gp<L, G, R, BATCH, true>(a, i0, n, m, ld, s);
+  } else if constexpr (std::is_same_v<R, double>) {
+    if (a.split == 2) return launch_moments_gp<L, G, R, BATCH, false, 2>(a, i0, n, m, ld, s);
+    if (a.split == 4) return launch_moments_gp<L, G, R, BATCH, false, 4>(a, i0, n, m, ld, s);
+    if (a.split == 8) return launch_moments_gp<L, G, R, BATCH, false, 8>(a, i0, n, m, ld, s);
   }
   launch_moments_gp<L, G, R, BATCH, false>(a, i0, n, m, ld, s);
 }
@@ -581,25 +630,30 @@ void launch_rev_g(const void* m, long ld, int n, const void* cb, void* mb, hipSt
   hipLaunchKernelGGL((k_program_rev<L, G, R>), dim3(nb), dim3(kLaneBlock), 0, s, (const R*)m, ld, n,
                      (const R*)cb, (R*)mb);
 }
-template <class L, int G, class R, bool BATCH, bool PERSIST>
+template <class L, int G, class R, bool BATCH, bool PERSIST, int K = 1>
 void launch_backward_gp(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                         int acc, double* wpart, double* watom, double* fown, hipStream_t s) {
-  const int nb = pair_grid(a, (n + kLaneBlock - 1) / kLaneBlock);
+  const int nb = pair_grid(a, split_tiles(n, K));
   if (a.ncheb == 8)
-    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 8, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 8, PERSIST, K>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
                        (const R*)mb, ld, g, acc, wpart, watom, fown);
   else if (a.ncheb == 10)
-    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 10, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 10, PERSIST, K>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
                        (const R*)mb, ld, g, acc, wpart, watom, fown);
   else
-    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 0, PERSIST>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
+    hipLaunchKernelGGL((k_backward<L, G, R, BATCH, 0, PERSIST, K>), dim3(nb), dim3(kLaneBlock), 0, s, a, i0, n,
                        (const R*)mb, ld, g, acc, wpart, watom, fown);
 }
+// the virial partials: one per workgroup, split_tiles(n, a.split) of them for a single system
 template <class L, int G, class R, bool BATCH>
 void launch_backward_g(const SysArgs& a, int i0, int n, const void* mb, long ld, double* g,
                        int acc, double* wpart, double* watom, double* fown, hipStream_t s) {
   if constexpr (BATCH) {
     if (a.queue) return launch_backward_gp<L, G, R, BATCH, true>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
+  } else if constexpr (std::is_same_v<R, double>) {
+    if (a.split == 2) return launch_backward_gp<L, G, R, BATCH, false, 2>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
+    if (a.split == 4) return launch_backward_gp<L, G, R, BATCH, false, 4>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
+    if (a.split == 8) return launch_backward_gp<L, G, R, BATCH, false, 8>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
   }
   launch_backward_gp<L, G, R, BATCH, false>(a, i0, n, mb, ld, g, acc, wpart, watom, fown, s);
 }

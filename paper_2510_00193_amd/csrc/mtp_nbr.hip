@@ -366,7 +366,7 @@ __global__ void k_rev(long long total, const int* __restrict__ off, const int* _
 //      network (every partner appears once in a row when each axis has at least three bins),
 //      the marked ones take the canonical test, and the sorted row of keys (j, n1, n2, n3) is
 //      written at fixed capacity.
-// k_rows_copy then writes the CSR arrays and k_rev_unique pairs the mirrors.  A brick whose staged
+// k_rows_copy then writes the CSR arrays and pairs the mirrors.  A brick whose staged
 // candidates exceed MAXC, or a row beyond ROWCAP, sets flag[3] and the caller takes the
 // unstaged path.
 constexpr int kBrickThreads = 256;
@@ -610,50 +610,90 @@ __global__ __launch_bounds__(kBrickThreads) void k_brick_rows(PlanArgs pa, Brick
         rj[t] = (int)(key >> 24);
         rs[t] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
         ++m;
+      } else if (t < 32) {
+        rj[t] = 0x7FFFFFFF;  // pad the first 32 slots: k_rows_copy ranks against them unmasked
       }
     }
     counts[i] = m;
   }
 }
 
-// Sorted fixed-capacity rows -> CSR j / packed shift: G lanes per row, lane t copies entry t.
+// Sorted fixed-capacity rows -> CSR j / packed shift, and the mirror index.  G lanes per row,
+// lane t takes entry t.  Rows built by k_brick_rows hold each partner once, sorted by partner,
+// and their first 32 slots are padded with INT_MAX, so the mirror of (i, j, n) is entry
+// off[j] + #{u : rows_j[j][u] < i}.  The wave counts cooperatively: in step v, the eight lanes
+// 8k..8k+7 read the eight 16-byte pieces of the first 32 slots of the row of lane 8v + k (one
+// 128-byte line per eight lanes instead of a line per lane), count the entries below that
+// lane's i, and sum over the eight lanes.  A row with all of its first 32 entries below i
+// continues alone, four entries at a time, up to counts[j].
 constexpr int kCsrThreads = 256;
+template <int CAP>
+__device__ __forceinline__ int mirror_rank(const int* __restrict__ rows_j, const int* __restrict__ counts,
+                                           int i, int j) {
+  const int l = threadIdx.x & 63;
+  // all exchanges first, then all eight loads (no branch between them, so they are in flight
+  // together: a lane without an entry reads row 0 and counts nothing)
+  int js[8], is[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int src = 8 * v + (l >> 3);
+    js[v] = __shfl(j, src, 64);
+    is[v] = __shfl(i, src, 64);
+  }
+  int4 q[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) q[v] = reinterpret_cast<const int4*>(rows_j + (long)max(js[v], 0) * CAP)[l & 7];
+  int rank = 0;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int x = is[v];
+    int part = js[v] >= 0 ? (q[v].x < x) + (q[v].y < x) + (q[v].z < x) + (q[v].w < x) : 0;
+    part += __shfl_xor(part, 1, 64);
+    part += __shfl_xor(part, 2, 64);
+    part += __shfl_xor(part, 4, 64);
+    const int got = __shfl(part, 8 * (l & 7), 64);
+    if ((l >> 3) == v) rank = got;
+  }
+  if (j >= 0 && rank == 32) {
+    const int cj = counts[j];
+    const int4* row = reinterpret_cast<const int4*>(rows_j + (long)j * CAP);
+    for (int u = 8; 4 * u < cj; ++u) {
+      const int4 v = row[u];
+      rank += (4 * u + 0 < cj && v.x < i) + (4 * u + 1 < cj && v.y < i) + (4 * u + 2 < cj && v.z < i) +
+              (4 * u + 3 < cj && v.w < i);
+    }
+  }
+  return rank;
+}
+
 template <int G, int CAP>
 __global__ __launch_bounds__(kCsrThreads) void k_rows_copy(int n, const int* __restrict__ rows_j,
                                                            const int* __restrict__ rows_s,
                                                            const int* __restrict__ counts,
                                                            const int* __restrict__ off, int* __restrict__ nj,
-                                                           int* __restrict__ shift) {
+                                                           int* __restrict__ shift, int* __restrict__ rev) {
+  static_assert(CAP >= 32 && CAP % 4 == 0 && CAP % G == 0 && 64 % G == 0 && G >= 32, "row layout");
   constexpr int R = kCsrThreads / G;
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int i = b * R + threadIdx.x / G, lane = threadIdx.x % G;
-  if (i >= n) return;
-  const int cnt = counts[i], o = off[i];
-  for (int t = lane; t < cnt; t += G) {
-    nj[o + t] = rows_j[(long)i * CAP + t];
-    shift[o + t] = rows_s[(long)i * CAP + t];
-  }
-}
-
-// rev of a list whose rows hold each partner once (the staged path): the mirror of (i, j, n) is
-// the entry of row j whose partner is i, found by a lower bound over row j's partner indices in
-// the CSR array (4 bytes an entry, so a row spans one or two cache lines).  G lanes per row.
-template <int G>
-__global__ __launch_bounds__(kCsrThreads) void k_rev_unique(int n, const int* __restrict__ off,
-                                                            const int* __restrict__ nj, int* __restrict__ rev) {
-  constexpr int R = kCsrThreads / G;
-  const int b = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int i = b * R + threadIdx.x / G, lane = threadIdx.x % G;
-  if (i >= n) return;
-  const int p0 = off[i], p1 = off[i + 1];
-  for (int p = p0 + lane; p < p1; p += G) {
-    const int j = nj[p];
-    int lo = off[j], hi = off[j + 1];  // first entry of row j with partner >= i
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (nj[mid] < i) lo = mid + 1; else hi = mid;
+  // no early exit: the rank count exchanges values across the whole wave
+  const int ic = min(i, n - 1);  // rows past the end read row n - 1 and write nothing
+  const int cnt = i < n ? counts[i] : 0, o = off[ic];
+  for (int t0 = 0; t0 < CAP; t0 += G) {
+    if (!__any(t0 < cnt)) break;
+    const int t = t0 + lane;
+    const bool has = t < cnt;
+    const int jr = rows_j[(long)ic * CAP + t], sr = rows_s[(long)ic * CAP + t];
+    const int j = has ? jr : -1;
+    if (has) {
+      nj[o + t] = j;
+      shift[o + t] = sr;
     }
-    rev[p] = lo;
+    if (rev) {
+      const int oj = off[max(j, 0)];
+      const int rank = mirror_rank<CAP>(rows_j, counts, i, j);
+      if (has) rev[o + t] = oj + rank;
+    }
   }
 }
 
@@ -995,12 +1035,10 @@ int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, dou
     if (n > 0) {
       if (w->row_cap == 64)
         hipLaunchKernelGGL((k_rows_copy<32, 64>), dim3((n + 7) / 8), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
-                           counts, off, nj, shift);
+                           counts, off, nj, shift, rev);
       else
         hipLaunchKernelGGL((k_rows_copy<64, 128>), dim3((n + 3) / 4), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
-                           counts, off, nj, shift);
-      if (rev)
-        hipLaunchKernelGGL((k_rev_unique<32>), dim3((n + 7) / 8), dim3(kCsrThreads), 0, s, n, off, nj, rev);
+                           counts, off, nj, shift, rev);
     }
     if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;
     return 0;

@@ -61,7 +61,8 @@ struct StaticLayout {
   size_t part = 0, flag = 0, eatom = 0, g = 0, fown = 0, wpart = 0, mom = 0, cbar = 0, mbar = 0, end = 0;
 };
 
-StaticLayout layout_for(const LevelOps& L, int n, long long npairs, bool need_eatom, bool backward, int chunk) {
+StaticLayout layout_for(const LevelOps& L, int n, long long npairs, bool need_eatom, bool backward, int chunk,
+                        int split) {
   StaticLayout s;
   size_t o = 0;
   s.part = o;
@@ -82,7 +83,7 @@ StaticLayout layout_for(const LevelOps& L, int n, long long npairs, bool need_ea
     s.fown = o;
     o += align_up((size_t)std::max(n, 1) * 3 * sizeof(double));
     s.wpart = o;
-    o += align_up((size_t)chain_wpart_blocks(n, chunk) * 6 * sizeof(double));
+    o += align_up((size_t)chain_wpart_blocks(n, chunk, split) * 6 * sizeof(double));
   }
   s.end = o;
   return s;
@@ -101,10 +102,11 @@ extern "C" int mtp_compute_static(mtp_model* m, const mtp_system* sys, const mtp
   // the model's chunk, shrunk in whole workgroups until the buffers fit: per-atom results and
   // the per-workgroup virial partials do not depend on the chunk when it is a multiple of 64
   int chunk = std::max(1, std::min(m->chunk, std::max(n, 1)));
-  StaticLayout lay = layout_for(m->ops, n, nl->n_pairs, !e_atom, backward, chunk);
+  const int split = pair_split(m, n);
+  StaticLayout lay = layout_for(m->ops, n, nl->n_pairs, !e_atom, backward, chunk, split);
   while (lay.end > kScratchBytes && chunk > kMinChunk) {
     chunk = std::max(kMinChunk, (chunk / 2 + kMinChunk - 1) / kMinChunk * kMinChunk);
-    lay = layout_for(m->ops, n, nl->n_pairs, !e_atom, backward, chunk);
+    lay = layout_for(m->ops, n, nl->n_pairs, !e_atom, backward, chunk, split);
   }
   if (lay.end > kScratchBytes)
     return mtp_fail(MTP_ERR_CAPACITY, "mtp_compute_static: " + std::to_string(n) + " atoms and " +

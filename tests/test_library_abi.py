@@ -41,3 +41,33 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_2510_00193_amd import _lib
     with pytest.raises(RuntimeError, match="missing"):
         _lib.open_library(str(tmp_path / "nope.so"))
+
+
+def test_ctypes_structures_match_the_header_layout(tmp_path):
+    """The binding's structures have the size and field offsets the C compiler gives the
+    header's structures (a field added on one side only would shift every later field)."""
+    import shutil
+    import subprocess
+    from paper_2510_00193_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mtp_params": _lib.MtpParams, "mtp_system": _lib.MtpSystem, "mtp_nlist": _lib.MtpNlist}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mtp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -594,7 +594,8 @@ extern "C" int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_n
   // per-chunk descriptor partials [chunk][na], then the descriptor itself
   if ((rc = m->bvals.reserve((size_t)na * ld * sizeof(double))) ||
       (rc = m->eatom.reserve((size_t)std::max(n, 1) * sizeof(double))) ||
-      (rc = m->dxi_part.reserve((size_t)(nchunks + 1) * na * sizeof(double))))
+      (rc = m->dxi_part.reserve((size_t)(nchunks + 1) * na * sizeof(double))) ||
+      (rc = m->rsum.reserve((size_t)na * kRowParts * sizeof(double))))
     return rc;
   double* bv = (double*)m->bvals.p;
   double* part = (double*)m->dxi_part.p;
@@ -605,7 +606,7 @@ extern "C" int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_n
     if ((rc = chain_work_reserve(m, n, use.n_pairs, false, &w))) return rc;
     rc = run_energy_chain(m, sys, use, (double*)m->eatom.p, false, bv, s, [&](int, int cn) {
       ProfScope ps(&m->prof, P_REDUCE, s);
-      launch_rowsum(bv, ld, 1, cn, na, part + chunk * na, 1, s);
+      launch_rowsum(bv, ld, 1, cn, na, part + chunk * na, 1, s, (double*)m->rsum.p);
       ++chunk;
     }, w);
     if (rc) return rc;
@@ -660,7 +661,8 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
       (rc = m->mbar.reserve((size_t)L.nmom * ld * 8)) || (rc = m->mdot.reserve((size_t)L.nmom * ld * 8)) ||
       (rc = m->cbard.reserve((size_t)L.ncomp * ld * 8)) || (rc = m->mbard.reserve((size_t)L.nmom * ld * 8)) ||
       (rc = m->xout.reserve((size_t)na * ld * 8)) || (rc = m->eatom.reserve((size_t)n * 8)) ||
-      (rc = m->dxi_part.reserve((size_t)na * nchunks * 8)) || (rc = m->cpart.reserve((size_t)nparts * K * 8)))
+      (rc = m->dxi_part.reserve((size_t)na * nchunks * 8)) || (rc = m->cpart.reserve((size_t)nparts * K * 8)) ||
+      (rc = m->rsum.reserve((size_t)std::max<long>(na, K) * kRowParts * 8)))
     return rc;
   SysArgs a = make_sys_args(m, sys, use);
   if (m->nsp > 1 && use.n_pairs > 0) {
@@ -710,12 +712,12 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
       part += cblk;
     }
     ProfScope ps(&m->prof, P_REDUCE, s);
-    launch_rowsum(xout, ld, 1, cn, na, dxp + c, nchunks, s);
+    launch_rowsum(xout, ld, 1, cn, na, dxp + c, nchunks, s, (double*)m->rsum.p);
   }
   {
     ProfScope ps(&m->prof, P_REDUCE, s);
     launch_rowsum(dxp, nchunks, 1, nchunks, na, d_linear, 1, s);
-    launch_rowsum(cpart, 1, K, part, (int)K, d_radial, 1, s);
+    launch_rowsum(cpart, 1, K, part, (int)K, d_radial, 1, s, (double*)m->rsum.p);
     launch_species_grad(sys->species, n, m->nsp, ebar, d_shift, s);
   }
   HIP_TRY(hipGetLastError());

@@ -60,6 +60,7 @@ struct mtp_model {
   DevBuf mom, cbar, mbar, bvals, g, fown, eatom, wpart;  // per-chunk / per-pair workspace
   DevBuf mdot, cbard, mbard, xout, dxi_part, cpart;   // parameter-adjoint workspace
   DevBuf plink, pfirst;                                 // per-species pair chains (adjoint)
+  DevBuf rsum;                                          // partials of long row sums
   DevBuf scratch;
   DevBuf flag;                                          // status word of the list check
   void* static_scratch = nullptr;                       // device address of the fixed scratch area

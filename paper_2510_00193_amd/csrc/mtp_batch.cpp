@@ -41,7 +41,7 @@ struct mtp_batch {
   std::vector<int> h_off;          // host copy of the CSR offsets (neighbour counts)
   // workspace
   DevBuf eatom, watom, g, fown, forces, energy, virial, mom, cbar, mbar, mdot, cbard, mbard, xout, dxi_part,
-      cpart, wpart, ebar_cfg, fbar, parts, zeros;
+      cpart, wpart, ebar_cfg, fbar, parts, zeros, rsum;
   DevBuf queue;                    // tile counters of the persistent pair-kernel launches
   int pgrid = 0;                   // workgroups of a persistent launch
   // schedule
@@ -97,7 +97,8 @@ static int reserve_run(mtp_batch* b) {
       (rc = b->xout.reserve(L.nalpha * ld * 8)) || (rc = b->dxi_part.reserve(L.nalpha * nchunks * 8)) ||
       (rc = b->cpart.reserve(nblk * L.adj.nagroup * K * 8)) || (rc = b->wpart.reserve(nblk * 6 * 8)) ||
       (rc = b->ebar_cfg.reserve(b->ncfg * 8)) || (rc = b->fbar.reserve(3 * n * 8)) ||
-      (rc = b->parts.reserve((b->ncfg + n) * 8)))
+      (rc = b->parts.reserve((b->ncfg + n) * 8)) ||
+      (rc = b->rsum.reserve(std::max<long>(L.nalpha, K) * kRowParts * 8)))
     return rc;
   return MTP_OK;
 }
@@ -284,12 +285,12 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
       part += cblk;
     }
     ProfScope ps(&m->prof, P_REDUCE, s);
-    launch_rowsum((const double*)b->xout.p, ld, 1, cn, L.nalpha, dxp + c, nchunks, s);
+    launch_rowsum((const double*)b->xout.p, ld, 1, cn, L.nalpha, dxp + c, nchunks, s, (double*)b->rsum.p);
   }
   ProfScope ps(&m->prof, P_REDUCE, s);
   launch_rowsum(dxp, nchunks, 1, nchunks, L.nalpha, d_linear, 1, s);
-  launch_rowsum(cpart, 1, KR, part, (int)KR, d_radial, 1, s);
-  launch_species_grad_cfg(b->species, (const int*)b->cfg.p, ebar, n, m->nsp, d_shift, s);
+  launch_rowsum(cpart, 1, KR, part, (int)KR, d_radial, 1, s, (double*)b->rsum.p);
+  launch_species_grad_cfg(b->species, (const int*)b->cfg.p, ebar, n, m->nsp, d_shift, (double*)b->rsum.p, s);
 }
 
 static int launch_run(mtp_batch* b, const double* e_target, const double* f_target, const double* ebar,

@@ -102,6 +102,20 @@ __global__ __launch_bounds__(kNT) void k_rowsum(const double* __restrict__ x, lo
   if (threadIdx.x == 0) out[(long)blockIdx.x * os] = v;
 }
 
+// First level of a long row sum: part[r * kRowParts + q] = sum over the q-th contiguous slice of
+// row r (grid kRowParts x rows, fixed order inside each slice)
+__global__ __launch_bounds__(kNT) void k_rowsum_part(const double* __restrict__ x, long rs, long es, long n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[kNT];
+  const long per = (n + kRowParts - 1) / kRowParts;
+  const long lo = (long)blockIdx.x * per, hi = min(n, lo + per);
+  const double* row = x + (long)blockIdx.y * rs;
+  double acc = 0.0;
+  for (long k = lo + threadIdx.x; k < hi; k += kNT) acc += row[k * es];
+  const double v = block_sum<kNT>(acc, sh);
+  if (threadIdx.x == 0) part[(long)blockIdx.y * kRowParts + blockIdx.x] = v;
+}
+
 // d(ebar E + fbar.F)/ds_t = ebar * (number of atoms of species t); integer counts are exact
 __global__ __launch_bounds__(kNT) void k_species_grad(const int* __restrict__ species, int n, int nsp,
                                                       double ebar, double* __restrict__ out) {
@@ -153,17 +167,21 @@ __global__ void k_loss_atoms(const double* __restrict__ f, const double* __restr
 }
 
 // ds_t = sum_i ebar_{cfg(i)} [z_i = t] (one workgroup per species, fixed order)
+// part[t * kRowParts + q] = sum of ebar[cfg[i]] over the atoms i of species t in the q-th slice
+// of the atoms (grid kRowParts x nsp); the parts are summed by k_rowsum
 __global__ __launch_bounds__(kNT) void k_species_grad_cfg(const int* __restrict__ species,
                                                           const int* __restrict__ cfg,
                                                           const double* __restrict__ ebar, int n,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ part) {
   __shared__ double sh[kNT];
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
+  const int per = (n + kRowParts - 1) / kRowParts;
+  const int lo = blockIdx.x * per, hi = min(n, lo + per);
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += kNT)
+  for (int i = lo + threadIdx.x; i < hi; i += kNT)
     if (species[i] == t) acc += ebar[cfg[i]];
   const double v = block_sum<kNT>(acc, sh);
-  if (threadIdx.x == 0) out[t] = v;
+  if (threadIdx.x == 0) part[t * kRowParts + blockIdx.x] = v;
 }
 
 // Per-species chains through each CSR row: pfirst[i][t] is the first pair of atom i whose
@@ -287,13 +305,20 @@ void launch_loss(const double* e, const double* e0, int ncfg, const double* f, c
 }
 
 void launch_species_grad_cfg(const int* species, const int* cfg, const double* ebar, int n, int nsp,
-                             double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_species_grad_cfg, dim3(nsp), dim3(kNT), 0, s, species, cfg, ebar, n, out);
+                             double* out, double* tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_species_grad_cfg, dim3(kRowParts, nsp), dim3(kNT), 0, s, species, cfg, ebar, n, tmp);
+  hipLaunchKernelGGL(k_rowsum, dim3(nsp), dim3(kNT), 0, s, tmp, (long)kRowParts, 1L, (long)kRowParts, out, 1L);
 }
 
 void launch_rowsum(const double* x, long rs, long es, long n, int rows, double* out, long os,
-                   hipStream_t s) {
+                   hipStream_t s, double* tmp) {
   if (rows <= 0) return;
+  if (tmp && n >= kRowSplitMin) {
+    // long rows: kRowParts workgroups per row, then one per row over the parts
+    hipLaunchKernelGGL(k_rowsum_part, dim3(kRowParts, rows), dim3(kNT), 0, s, x, rs, es, n, tmp);
+    hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(kNT), 0, s, tmp, (long)kRowParts, 1L, (long)kRowParts, out, os);
+    return;
+  }
   hipLaunchKernelGGL(k_rowsum, dim3(rows), dim3(kNT), 0, s, x, rs, es, n, out, os);
 }
 

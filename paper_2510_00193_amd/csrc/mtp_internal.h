@@ -123,16 +123,21 @@ void launch_sum_parts(const double* x, long n, long stride, int ncomp, double* p
                       hipStream_t s);
 void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream_t s);
 
-// out[r * os] = sum_{k < n} x[r * rs + k * es], r < rows (deterministic)
+// out[r * os] = sum_{k < n} x[r * rs + k * es], r < rows (deterministic: the order depends on n
+// and on whether tmp is given).  tmp (optional, rows * kRowParts doubles) lets rows of at least
+// kRowSplitMin terms be summed by kRowParts workgroups each.
+constexpr int kRowParts = 64;
+constexpr long kRowSplitMin = 16384;
 void launch_rowsum(const double* x, long rs, long es, long n, int rows, double* out, long os,
-                   hipStream_t s);
+                   hipStream_t s, double* tmp = nullptr);
 void launch_species_grad(const int* species, int n, int nsp, double ebar, double* out, hipStream_t s);
 void launch_segsum(const double* x, long stride, const int* seg_off, int nseg, int ncomp, double* out,
                    long os, hipStream_t s);
 void launch_loss(const double* e, const double* e0, int ncfg, const double* f, const double* f0, long n,
                  double* ebar, double* fbar, double* part_cfg, double* part_atoms, hipStream_t s);
+// d/ds_t of sum_c ebar_c E_c over a batch; tmp holds nsp * kRowParts doubles
 void launch_species_grad_cfg(const int* species, const int* cfg, const double* ebar, int n, int nsp,
-                             double* out, hipStream_t s);
+                             double* out, double* tmp, hipStream_t s);
 
 // grade (mtp_grade.hip)
 void launch_grade(const double* B, long ld, int n, const double* ainv, int na, int split,

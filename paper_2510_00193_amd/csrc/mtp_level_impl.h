@@ -328,7 +328,17 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
     const double rix = a.pos[3 * i], riy = a.pos[3 * i + 1], riz = a.pos[3 * i + 2];
     const int zi = clamp_species(a.species[i], a.nsp);
     const R* cz = csh + zi * a.nsp * L::NMU * a.ncheb;
+    // the gradient of a pair is stored at the start of the next pair's body, after that
+    // pair's list and position loads: the wait for those loads at the end of the body then
+    // does not also wait for a store issued just before it (one counter covers both)
+    int pq = -1;
+    double qx = 0.0, qy = 0.0, qz = 0.0;
     for_pairs<K>(a, i, sub, H, rix, riy, riz, [&](int p, int, int zj, double dx, double dy, double dz, double r) {
+      if (pq >= 0) {
+        g[3L * pq] = qx;
+        g[3L * pq + 1] = qy;
+        g[3L * pq + 2] = qz;
+      }
       R f[L::NMU], fp[L::NMU];
       radial<R, L::NMU, NC>((R)r, (R)a.sa, (R)a.sb, (R)a.rcut, cz + zj * L::NMU * a.ncheb, a.ncheb, f, fp);
       R rgx = R(0), rgy = R(0), rgz = R(0), ru = R(0);
@@ -342,9 +352,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
         g[3L * p + 1] += gy;
         g[3L * p + 2] += gz;
       } else {
-        g[3L * p] = gx;
-        g[3L * p + 1] = gy;
-        g[3L * p + 2] = gz;
+        pq = p;
+        qx = gx;
+        qy = gy;
+        qz = gz;
       }
       fo[0] += gx;
       fo[1] += gy;
@@ -356,6 +367,11 @@ __global__ __launch_bounds__(kLaneBlock) void k_backward(SysArgs a, int i0, int 
       w[4] -= dx * gz;
       w[5] -= dy * gz;
     });
+    if (pq >= 0) {
+      g[3L * pq] = qx;
+      g[3L * pq + 1] = qy;
+      g[3L * pq + 2] = qz;
+    }
     if constexpr (BATCH) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) watom[6L * i + k] = accumulate ? watom[6L * i + k] + w[k] : w[k];

@@ -618,81 +618,101 @@ __global__ __launch_bounds__(kBrickThreads) void k_brick_rows(PlanArgs pa, Brick
   }
 }
 
-// Sorted fixed-capacity rows -> CSR j / packed shift, and the mirror index.  G lanes per row,
-// lane t takes entry t.  Rows built by k_brick_rows hold each partner once, sorted by partner,
-// and their first 32 slots are padded with INT_MAX, so the mirror of (i, j, n) is entry
-// off[j] + #{u : rows_j[j][u] < i}.  The wave counts cooperatively: in step v, the eight lanes
-// 8k..8k+7 read the eight 16-byte pieces of the first 32 slots of the row of lane 8v + k (one
+// Sorted fixed-capacity rows -> CSR j / packed shift, and the mirror index.  Rows built by
+// k_brick_rows hold each partner once, sorted by partner, and their first 32 slots are padded
+// with INT_MAX, so the mirror of (i, j, n) is entry off[j] + #{u : rows_j[j][u] < i}.
+// G lanes per row, E entries per lane (entries t and t + G of the row); a wave holds 64 / G rows
+// (one entry per lane measured fastest: two per lane halve the waves but slowed the copy by a third).
+// The wave counts cooperatively: in step v of entry slot e, the eight lanes 8k..8k+7 read the
+// eight 16-byte pieces of the first 32 slots of the row of lane 8(v % 8) + k's entry e (one
 // 128-byte line per eight lanes instead of a line per lane), count the entries below that
-// lane's i, and sum over the eight lanes.  A row with all of its first 32 entries below i
-// continues alone, four entries at a time, up to counts[j].
+// lane's i and sum over the eight lanes.  All exchanges and loads of a lane are issued before
+// the first count, so a wave has every load of its rows in flight at once.  A row with all of
+// its first 32 entries below i continues alone, four entries at a time, up to counts[j].
 constexpr int kCsrThreads = 256;
-template <int CAP>
-__device__ __forceinline__ int mirror_rank(const int* __restrict__ rows_j, const int* __restrict__ counts,
-                                           int i, int j) {
+template <int CAP, int E>
+__device__ __forceinline__ void mirror_rank(const int* __restrict__ rows_j, const int* __restrict__ counts,
+                                            int i, const int (&j)[E], int (&rank)[E]) {
   const int l = threadIdx.x & 63;
-  // all exchanges first, then all eight loads (no branch between them, so they are in flight
-  // together: a lane without an entry reads row 0 and counts nothing)
-  int js[8], is[8];
+  int js[E][8], is[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int src = 8 * v + (l >> 3);
-    js[v] = __shfl(j, src, 64);
     is[v] = __shfl(i, src, 64);
-  }
-  int4 q[8];
 #pragma unroll
-  for (int v = 0; v < 8; ++v) q[v] = reinterpret_cast<const int4*>(rows_j + (long)max(js[v], 0) * CAP)[l & 7];
-  int rank = 0;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const int x = is[v];
-    int part = js[v] >= 0 ? (q[v].x < x) + (q[v].y < x) + (q[v].z < x) + (q[v].w < x) : 0;
-    part += __shfl_xor(part, 1, 64);
-    part += __shfl_xor(part, 2, 64);
-    part += __shfl_xor(part, 4, 64);
-    const int got = __shfl(part, 8 * (l & 7), 64);
-    if ((l >> 3) == v) rank = got;
+    for (int e = 0; e < E; ++e) js[e][v] = __shfl(j[e], src, 64);
   }
-  if (j >= 0 && rank == 32) {
-    const int cj = counts[j];
-    const int4* row = reinterpret_cast<const int4*>(rows_j + (long)j * CAP);
-    for (int u = 8; 4 * u < cj; ++u) {
-      const int4 v = row[u];
-      rank += (4 * u + 0 < cj && v.x < i) + (4 * u + 1 < cj && v.y < i) + (4 * u + 2 < cj && v.z < i) +
-              (4 * u + 3 < cj && v.w < i);
+  int4 q[E][8];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+      q[e][v] = reinterpret_cast<const int4*>(rows_j + (long)max(js[e][v], 0) * CAP)[l & 7];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    rank[e] = 0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int x = is[v];
+      const int4 w = q[e][v];
+      int part = js[e][v] >= 0 ? (w.x < x) + (w.y < x) + (w.z < x) + (w.w < x) : 0;
+      part += __shfl_xor(part, 1, 64);
+      part += __shfl_xor(part, 2, 64);
+      part += __shfl_xor(part, 4, 64);
+      const int got = __shfl(part, 8 * (l & 7), 64);
+      if ((l >> 3) == v) rank[e] = got;
     }
   }
-  return rank;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (j[e] >= 0 && rank[e] == 32) {
+      const int cj = counts[j[e]];
+      const int4* row = reinterpret_cast<const int4*>(rows_j + (long)j[e] * CAP);
+      for (int u = 8; 4 * u < cj; ++u) {
+        const int4 w = row[u];
+        rank[e] += (4 * u + 0 < cj && w.x < i) + (4 * u + 1 < cj && w.y < i) + (4 * u + 2 < cj && w.z < i) +
+                   (4 * u + 3 < cj && w.w < i);
+      }
+    }
+  }
 }
 
-template <int G, int CAP>
+template <int G, int E, int CAP>
 __global__ __launch_bounds__(kCsrThreads) void k_rows_copy(int n, const int* __restrict__ rows_j,
                                                            const int* __restrict__ rows_s,
                                                            const int* __restrict__ counts,
                                                            const int* __restrict__ off, int* __restrict__ nj,
                                                            int* __restrict__ shift, int* __restrict__ rev) {
-  static_assert(CAP >= 32 && CAP % 4 == 0 && CAP % G == 0 && 64 % G == 0 && G >= 32, "row layout");
+  static_assert(CAP >= 32 && CAP % 4 == 0 && CAP % (G * E) == 0 && 64 % G == 0, "row layout");
   constexpr int R = kCsrThreads / G;
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int i = b * R + threadIdx.x / G, lane = threadIdx.x % G;
   // no early exit: the rank count exchanges values across the whole wave
   const int ic = min(i, n - 1);  // rows past the end read row n - 1 and write nothing
   const int cnt = i < n ? counts[i] : 0, o = off[ic];
-  for (int t0 = 0; t0 < CAP; t0 += G) {
+  for (int t0 = 0; t0 < CAP; t0 += G * E) {
     if (!__any(t0 < cnt)) break;
-    const int t = t0 + lane;
-    const bool has = t < cnt;
-    const int jr = rows_j[(long)ic * CAP + t], sr = rows_s[(long)ic * CAP + t];
-    const int j = has ? jr : -1;
-    if (has) {
-      nj[o + t] = j;
-      shift[o + t] = sr;
+    int j[E], sr[E], oj[E], rank[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = t0 + lane + e * G;
+      const int jr = rows_j[(long)ic * CAP + t];
+      sr[e] = rows_s[(long)ic * CAP + t];
+      j[e] = t < cnt ? jr : -1;
     }
     if (rev) {
-      const int oj = off[max(j, 0)];
-      const int rank = mirror_rank<CAP>(rows_j, counts, i, j);
-      if (has) rev[o + t] = oj + rank;
+#pragma unroll
+      for (int e = 0; e < E; ++e) oj[e] = off[max(j[e], 0)];
+      mirror_rank<CAP, E>(rows_j, counts, i, j, rank);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = t0 + lane + e * G;
+      if (t < cnt) {
+        nj[o + t] = j[e];
+        shift[o + t] = sr[e];
+        if (rev) rev[o + t] = oj[e] + rank[e];
+      }
     }
   }
 }
@@ -1034,10 +1054,10 @@ int nbr_fill(const NbrPlan& plan, const double* pos, int n, const double* H, dou
     int* counts = w->get<int>(S_COUNTS, n);
     if (n > 0) {
       if (w->row_cap == 64)
-        hipLaunchKernelGGL((k_rows_copy<32, 64>), dim3((n + 7) / 8), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
+        hipLaunchKernelGGL((k_rows_copy<32, 1, 64>), dim3((n + 7) / 8), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
                            counts, off, nj, shift, rev);
       else
-        hipLaunchKernelGGL((k_rows_copy<64, 128>), dim3((n + 3) / 4), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
+        hipLaunchKernelGGL((k_rows_copy<64, 1, 128>), dim3((n + 3) / 4), dim3(kCsrThreads), 0, s, n, rows_j, rows_s,
                            counts, off, nj, shift, rev);
     }
     if (hipGetLastError() != hipSuccess) return MTP_ERR_HIP;

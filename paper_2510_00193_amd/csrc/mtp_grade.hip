@@ -29,6 +29,7 @@ constexpr int kMaxTiles = 8;          // 16-column MFMA tiles per column sweep
 constexpr int kPanelBytes = 120 * 1024;  // LDS panel of Ainv
 constexpr int kRing = 4;              // K steps of atom operands loaded ahead
 constexpr int kTpw = 2;               // 16-atom tiles per wave
+constexpr int kResMax = 4;            // last columns (beyond whole 16-column tiles) taken on VALU
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -42,6 +43,11 @@ __device__ __forceinline__ double max16(double v) {
 
 // One panel: columns [c_lo, c_lo + pw) of Ainv, pw a multiple of 16; kp = na rounded up to 4.
 // A wave takes kTpw 16-atom tiles at once, so every Ainv operand read from LDS feeds kTpw MFMAs.
+// In the split form, when the panel's valid columns end at most kResMax columns past a whole
+// 16-column tile, those columns are not padded to a tile of three binary32 products: each lane
+// accumulates them with binary64 FMAs over its own K slice (the atom operand it already holds),
+// and the four K slices of an atom are summed with lane exchanges after the K loop.  (In the
+// binary64 form the padded tile costs less than the VALU columns.)
 template <bool SPLIT>
 __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict__ B, long ld, int n,
                                                        const double* __restrict__ ainv, int na, int c_lo,
@@ -58,6 +64,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict_
   const int row = lane & 15;      // atom row supplied as A operand / column of D
   const int kq = lane >> 4;       // k index inside a K=4 step, and row quad of D
   const int ksteps = kp / 4;
+  const int valid = min(pw, na - c_lo);
+  int mcols = valid / 16 * 16, nres = valid - mcols;  // matrix-core columns, VALU columns
+  if (nres > kResMax || (!SPLIT && nres > 0)) {  // binary64 matrix cores: padding measured faster
+    mcols += 16;
+    nres = 0;
+  }
   const int ngroups = (n + 16 * kTpw - 1) / (16 * kTpw);
   const int stride = gridDim.x * kWaves;
   for (int grp = xcd_logical_block(blockIdx.x, gridDim.x) * kWaves + wave; grp < ngroups; grp += stride) {
@@ -69,13 +81,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict_
       atom_ok[h] = i0 + 16 * h + row < n;
       bp[h] = B + i0 + 16 * h + row;
     }
-    double rmax[kTpw][4];
+    double rmax[kTpw][4], res[kTpw][kResMax];
 #pragma unroll
-    for (int h = 0; h < kTpw; ++h)
+    for (int h = 0; h < kTpw; ++h) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) rmax[h][r] = 0.0;
-    for (int c0 = 0; c0 < pw; c0 += 16 * kMaxTiles) {
-      const int nt = min(kMaxTiles, (pw - c0) / 16);
+#pragma unroll
+      for (int c = 0; c < kResMax; ++c) res[h][c] = 0.0;
+    }
+    // the VALU columns ride along the first column sweep, which loads the atom operands anyway
+    for (int c0 = 0; c0 < max(mcols, 1); c0 += 16 * kMaxTiles) {
+      const int nt = min(kMaxTiles, (mcols - c0) / 16);
       v4d acc[kTpw][kMaxTiles];
 #pragma unroll
       for (int h = 0; h < kTpw; ++h)
@@ -110,6 +126,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict_
               }
             }
             const double* srow = sa + (ks * 4 + kq) * pw + c0 + row;
+            if (c0 == 0 && nres > 0) {
+              const double* rrow = sa + (ks * 4 + kq) * pw + mcols;
+#pragma unroll
+              for (int c = 0; c < kResMax; ++c) {
+                if (c < nres) {
+                  const double bv = rrow[c];
+#pragma unroll
+                  for (int h = 0; h < kTpw; ++h) res[h][c] = fma(a[h], bv, res[h][c]);
+                }
+              }
+            }
 #pragma unroll
             for (int t = 0; t < kMaxTiles; ++t) {
               if (t < nt) {
@@ -151,12 +178,27 @@ __global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict_
         }
       }
     }
+    // VALU columns: sum the four K slices of each atom (lanes row, row + 16, row + 32, row + 48),
+    // then the largest magnitude over the columns, held by every lane of the atom
+    double mres[kTpw];
+#pragma unroll
+    for (int h = 0; h < kTpw; ++h) {
+      mres[h] = 0.0;
+#pragma unroll
+      for (int c = 0; c < kResMax; ++c) {
+        double v = res[h][c];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (c < nres) mres[h] = fmax(mres[h], fabs(v));
+      }
+    }
 #pragma unroll
     for (int h = 0; h < kTpw; ++h)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double m = max16(rmax[h][r]);
-        const int out = i0 + 16 * h + (SPLIT ? 4 * kq + r : 4 * r + kq);
+        const int a = SPLIT ? 4 * kq + r : 4 * r + kq;  // atom of the tile whose row max this is
+        const double m = fmax(max16(rmax[h][r]), __shfl(mres[h], a, 64));
+        const int out = i0 + 16 * h + a;
         if (row == 0 && out < n) grade[out] = first ? m : fmax(grade[out], m);
       }
   }

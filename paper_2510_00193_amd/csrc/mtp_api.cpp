@@ -495,7 +495,9 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
 // Energy reduction, force gather and virial reduction after the chain (part: 6 kSumParts doubles).
 int finish_compute(mtp_model* m, const mtp_nlist& nl, int n, const double* ea, const ChainWork& w,
                    double* part, double* energy, double* forces, double* virial, hipStream_t s) {
-  if (energy) {
+  // small systems: energy and virial sums in one launch after the gather (latency)
+  const bool small = n > 0 && n <= kSmallSumMax && w.wblocks <= kSmallSumMax;
+  if (energy && !small) {
     ProfScope ps(&m->prof, P_REDUCE, s);
     launch_sum_parts(ea, n, 1, 1, part, energy, s);
   }
@@ -503,12 +505,16 @@ int finish_compute(mtp_model* m, const mtp_nlist& nl, int n, const double* ea, c
     ProfScope ps(&m->prof, P_GATHER, s);
     launch_gather_forces(nl.off, nl.rev, w.g, w.fown, n, nl.n_pairs, forces, s);
   }
-  if (virial) {
+  if (virial && !small) {
     ProfScope ps(&m->prof, P_REDUCE, s);
     if (n > 0)
       launch_sum_parts(w.wpart, w.wblocks, 6, 6, part, virial, s);
     else
       launch_fill(virial, 6, 0.0, s);
+  }
+  if (small && (energy || virial)) {
+    ProfScope ps(&m->prof, P_REDUCE, s);
+    launch_sum_small(ea, n, virial ? w.wpart : nullptr, virial ? w.wblocks : 0, energy, virial, s);
   }
   HIP_TRY(hipGetLastError());
   return MTP_OK;

@@ -338,6 +338,34 @@ void launch_gather_forces(const int* off, const int* rev, const double* g, const
                        forces);
 }
 
+// Energy and virial of a small system in one workgroup: energy = sum_i ea[i] (n terms) and
+// virial[k] = sum_b wpart[6 b + k] (nb partials), each a fixed-order tree over the threads.
+__global__ __launch_bounds__(kSmallSumThreads) void k_sum_small(const double* __restrict__ ea, long n,
+                                                                const double* __restrict__ wpart, long nb,
+                                                                double* __restrict__ energy,
+                                                                double* __restrict__ virial) {
+  __shared__ double sh[kSmallSumThreads];
+  if (energy) {
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += kSmallSumThreads) acc += ea[i];
+    const double v = block_sum<kSmallSumThreads>(acc, sh);
+    if (threadIdx.x == 0) energy[0] = v;
+  }
+  if (virial) {
+    for (int k = 0; k < 6; ++k) {
+      double acc = 0.0;
+      for (long b = threadIdx.x; b < nb; b += kSmallSumThreads) acc += wpart[6 * b + k];
+      const double v = block_sum<kSmallSumThreads>(acc, sh);
+      if (threadIdx.x == 0) virial[k] = v;
+    }
+  }
+}
+
+void launch_sum_small(const double* ea, long n, const double* wpart, long nb, double* energy, double* virial,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(kSmallSumThreads), 0, s, ea, n, wpart, nb, energy, virial);
+}
+
 // out[c] = sum_i x[i * stride + c] for c < ncomp; part holds ncomp * kPartBlocks doubles.
 void launch_sum_parts(const double* x, long n, long stride, int ncomp, double* part, double* out,
                       hipStream_t s) {

@@ -119,6 +119,12 @@ void launch_gather_forces(const int* off, const int* rev, const double* g, const
 void launch_sum(const double* x, long n, long stride, double* out, hipStream_t s);
 // Two-level deterministic sums of ncomp strided components (part: ncomp * kSumParts doubles).
 constexpr int kSumParts = 256;
+// energy (ea over n atoms) and virial (nb per-workgroup partials) of a small system in one
+// launch; either output may be null.  For n and nb up to kSmallSumMax.
+constexpr int kSmallSumThreads = 1024;
+constexpr long kSmallSumMax = 8192;
+void launch_sum_small(const double* ea, long n, const double* wpart, long nb, double* energy, double* virial,
+                      hipStream_t s);
 void launch_sum_parts(const double* x, long n, long stride, int ncomp, double* part, double* out,
                       hipStream_t s);
 void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream_t s);

@@ -2,7 +2,7 @@
 // on the matrix cores, with the row max-abs taken in the epilogue (the product never leaves
 // registers).  B comes in [alpha][atom] layout (one chunk), Ainv is row-major n x n.
 //
-// A workgroup of kWaves waves stages a panel of Ainv (all rows, up to kPanelBytes of columns,
+// A workgroup of several waves stages a panel of Ainv (all rows, up to kPanelBytes of columns,
 // zero-padded to whole 16x16 tiles) in LDS once and keeps it there while its waves walk their
 // 16-atom tiles (a grid of about one workgroup per CU): every MFMA takes its Ainv operand from
 // LDS and the atom operand from B, loaded kRing K steps ahead (global-memory latency is
@@ -24,11 +24,17 @@
 namespace mtp {
 namespace {
 
-constexpr int kWaves = 8;             // waves per workgroup (two per SIMD)
+// Workgroup shape per form (measured at 250,000 atoms, level 16): the binary64 form runs four
+// waves of one 16-atom tile per SIMD (0.168 ms, against 0.175 ms for two waves of two tiles);
+// the split form, with three products per tile, two waves of two tiles (0.375 vs 0.404 ms).
+template <bool SPLIT>
+struct GradeShape {
+  static constexpr int waves = SPLIT ? 8 : 16;  // waves per workgroup
+  static constexpr int tpw = SPLIT ? 2 : 1;     // 16-atom tiles per wave
+};
 constexpr int kMaxTiles = 8;          // 16-column MFMA tiles per column sweep
 constexpr int kPanelBytes = 120 * 1024;  // LDS panel of Ainv
 constexpr int kRing = 4;              // K steps of atom operands loaded ahead
-constexpr int kTpw = 2;               // 16-atom tiles per wave
 constexpr int kResMax = 4;            // last columns (beyond whole 16-column tiles) taken on VALU
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -42,16 +48,18 @@ __device__ __forceinline__ double max16(double v) {
 }
 
 // One panel: columns [c_lo, c_lo + pw) of Ainv, pw a multiple of 16; kp = na rounded up to 4.
-// A wave takes kTpw 16-atom tiles at once, so every Ainv operand read from LDS feeds kTpw MFMAs.
+// A wave takes kTpw 16-atom tiles at once, so every Ainv operand read from LDS feeds kTpw MFMAs
+// (three per tile in the split form).
 // In the split form, when the panel's valid columns end at most kResMax columns past a whole
 // 16-column tile, those columns are not padded to a tile of three binary32 products: each lane
 // accumulates them with binary64 FMAs over its own K slice (the atom operand it already holds),
 // and the four K slices of an atom are summed with lane exchanges after the K loop.  (In the
 // binary64 form the padded tile costs less than the VALU columns.)
 template <bool SPLIT>
-__global__ __launch_bounds__(64 * kWaves) void k_grade(const double* __restrict__ B, long ld, int n,
+__global__ __launch_bounds__(64 * GradeShape<SPLIT>::waves) void k_grade(const double* __restrict__ B, long ld, int n,
                                                        const double* __restrict__ ainv, int na, int c_lo,
                                                        int pw, int first, double* __restrict__ grade) {
+  constexpr int kWaves = GradeShape<SPLIT>::waves, kTpw = GradeShape<SPLIT>::tpw;
   extern __shared__ double sa[];  // [kp][pw]
   const int kp = (na + 3) & ~3;
   for (int idx = threadIdx.x; idx < kp * pw; idx += 64 * kWaves) {
@@ -251,10 +259,12 @@ void launch_grade(const double* B, long ld, int n, const double* ainv, int na, i
   const int ncol = (na + 15) / 16 * 16;
   int pw = (int)(kPanelBytes / (sizeof(double) * kp)) / 16 * 16;
   pw = std::max(16, std::min(pw, ncol));
-  const int groups = (n + 16 * kTpw - 1) / (16 * kTpw);
+  const int waves = split ? GradeShape<true>::waves : GradeShape<false>::waves;
+  const int tpw = split ? GradeShape<true>::tpw : GradeShape<false>::tpw;
+  const int groups = (n + 16 * tpw - 1) / (16 * tpw);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int nb = std::max(1, std::min((groups + kWaves - 1) / kWaves, ncu));
+  const int nb = std::max(1, std::min((groups + waves - 1) / waves, ncu));
   const size_t lds = sizeof(double) * kp * pw;
   static bool attr_set = false;  // allow the panel beyond the default dynamic LDS limit
   if (!attr_set) {
@@ -265,9 +275,9 @@ void launch_grade(const double* B, long ld, int n, const double* ainv, int na, i
   for (int c = 0; c < ncol; c += pw) {
     const int w = std::min(pw, ncol - c);
     if (split)
-      hipLaunchKernelGGL((k_grade<true>), dim3(nb), dim3(64 * kWaves), lds, s, B, ld, n, ainv, na, c, w, c == 0, grade);
+      hipLaunchKernelGGL((k_grade<true>), dim3(nb), dim3(64 * waves), lds, s, B, ld, n, ainv, na, c, w, c == 0, grade);
     else
-      hipLaunchKernelGGL((k_grade<false>), dim3(nb), dim3(64 * kWaves), lds, s, B, ld, n, ainv, na, c, w, c == 0, grade);
+      hipLaunchKernelGGL((k_grade<false>), dim3(nb), dim3(64 * waves), lds, s, B, ld, n, ainv, na, c, w, c == 0, grade);
   }
 }
 

@@ -492,29 +492,33 @@ int run_energy_chain(mtp_model* m, const mtp_system* sys, const mtp_nlist& nl, d
   return MTP_OK;
 }
 
-// Energy reduction, force gather and virial reduction after the chain (part: 6 kSumParts doubles).
+// Energy reduction, force gather and virial reduction after the chain (part: 7 kSumParts doubles).
 int finish_compute(mtp_model* m, const mtp_nlist& nl, int n, const double* ea, const ChainWork& w,
                    double* part, double* energy, double* forces, double* virial, hipStream_t s) {
-  // small systems: energy and virial sums in one launch after the gather (latency)
-  const bool small = n > 0 && n <= kSmallSumMax && w.wblocks <= kSmallSumMax;
-  if (energy && !small) {
-    ProfScope ps(&m->prof, P_REDUCE, s);
-    launch_sum_parts(ea, n, 1, 1, part, energy, s);
-  }
   if (forces && n > 0) {
     ProfScope ps(&m->prof, P_GATHER, s);
     launch_gather_forces(nl.off, nl.rev, w.g, w.fown, n, nl.n_pairs, forces, s);
   }
-  if (virial && !small) {
-    ProfScope ps(&m->prof, P_REDUCE, s);
-    if (n > 0)
-      launch_sum_parts(w.wpart, w.wblocks, 6, 6, part, virial, s);
-    else
-      launch_fill(virial, 6, 0.0, s);
+  if (!energy && !virial) {
+    HIP_TRY(hipGetLastError());
+    return MTP_OK;
   }
-  if (small && (energy || virial)) {
-    ProfScope ps(&m->prof, P_REDUCE, s);
+  ProfScope ps(&m->prof, P_REDUCE, s);
+  // small systems: energy and virial in one launch (latency); otherwise both two-level sums
+  // share their launches
+  const bool small = n > 0 && n <= kSmallSumMax && w.wblocks <= kSmallSumMax;
+  if (small) {
     launch_sum_small(ea, n, virial ? w.wpart : nullptr, virial ? w.wblocks : 0, energy, virial, s);
+  } else if (n > 0 && energy && virial) {
+    launch_sum_parts2(ea, n, 1, 1, energy, w.wpart, w.wblocks, 6, 6, virial, part, s);
+  } else {
+    if (energy) launch_sum_parts(ea, n, 1, 1, part, energy, s);
+    if (virial) {
+      if (n > 0)
+        launch_sum_parts(w.wpart, w.wblocks, 6, 6, part, virial, s);
+      else
+        launch_fill(virial, 6, 0.0, s);
+    }
   }
   HIP_TRY(hipGetLastError());
   return MTP_OK;
@@ -540,7 +544,7 @@ extern "C" int mtp_compute(mtp_model* m, const mtp_system* sys, const mtp_nlist*
   if (n > 0) {
     if ((rc = run_energy_chain(m, sys, use, ea, backward, nullptr, s, nullptr, w))) return rc;
   }
-  if ((rc = m->scratch.reserve(6 * kSumParts * sizeof(double)))) return rc;
+  if ((rc = m->scratch.reserve(7 * kSumParts * sizeof(double)))) return rc;
   return finish_compute(m, use, n, ea, w, (double*)m->scratch.p, energy, forces, virial, s);
 }
 

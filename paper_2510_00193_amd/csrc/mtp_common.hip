@@ -81,6 +81,38 @@ __global__ __launch_bounds__(kNT) void k_sum_final(const double* __restrict__ pa
   if (threadIdx.x == 0) out[c] = v;
 }
 
+// The same two-level sums over two strided arrays at once (components c < nc1 of x1, then the
+// nc2 components of x2): one launch of partials and one of totals instead of two each; every
+// component's slices and order are those of k_sum_part / k_sum_final.
+__global__ __launch_bounds__(kNT) void k_sum_part2(const double* __restrict__ x1, long n1, long st1, int nc1,
+                                                   const double* __restrict__ x2, long n2, long st2,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[kNT];
+  const int c = blockIdx.y;
+  const bool first = c < nc1;
+  const double* x = first ? x1 : x2;
+  const long n = first ? n1 : n2, stride = first ? st1 : st2;
+  const int comp = first ? c : c - nc1;
+  const long per = (n + kPartBlocks - 1) / kPartBlocks;
+  const long lo = (long)blockIdx.x * per, hi = min(n, lo + per);
+  double acc = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += kNT) acc += x[i * stride + comp];
+  const double v = block_sum<kNT>(acc, sh);
+  if (threadIdx.x == 0) part[(long)c * kPartBlocks + blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kNT) void k_sum_final2(const double* __restrict__ part, int nc1,
+                                                    double* __restrict__ out1, double* __restrict__ out2) {
+  __shared__ double sh[kNT];
+  const int c = blockIdx.x;
+  const double v = block_sum<kNT>(threadIdx.x < kPartBlocks ? part[(long)c * kPartBlocks + threadIdx.x] : 0.0, sh);
+  if (threadIdx.x == 0) {
+    if (c < nc1) out1[c] = v;
+    else out2[c - nc1] = v;
+  }
+}
+
+
 // one workgroup: thread t sums x[t], x[t + T], ... then a fixed tree
 __global__ __launch_bounds__(kSumThreads) void k_sum(const double* __restrict__ x, long n,
                                                      long stride, double* __restrict__ out) {
@@ -364,6 +396,13 @@ __global__ __launch_bounds__(kSmallSumThreads) void k_sum_small(const double* __
 void launch_sum_small(const double* ea, long n, const double* wpart, long nb, double* energy, double* virial,
                       hipStream_t s) {
   hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(kSmallSumThreads), 0, s, ea, n, wpart, nb, energy, virial);
+}
+
+void launch_sum_parts2(const double* x1, long n1, long st1, int nc1, double* out1, const double* x2, long n2,
+                       long st2, int nc2, double* out2, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_part2, dim3(kPartBlocks, nc1 + nc2), dim3(kNT), 0, s, x1, n1, st1, nc1, x2, n2, st2,
+                     part);
+  hipLaunchKernelGGL(k_sum_final2, dim3(nc1 + nc2), dim3(kNT), 0, s, part, nc1, out1, out2);
 }
 
 // out[c] = sum_i x[i * stride + c] for c < ncomp; part holds ncomp * kPartBlocks doubles.

@@ -125,6 +125,10 @@ constexpr int kSmallSumThreads = 1024;
 constexpr long kSmallSumMax = 8192;
 void launch_sum_small(const double* ea, long n, const double* wpart, long nb, double* energy, double* virial,
                       hipStream_t s);
+// launch_sum_parts over two arrays in one pair of launches (part: (nc1 + nc2) * kSumParts
+// doubles); each output equals what launch_sum_parts gives for its array
+void launch_sum_parts2(const double* x1, long n1, long st1, int nc1, double* out1, const double* x2, long n2,
+                       long st2, int nc2, double* out2, double* part, hipStream_t s);
 void launch_sum_parts(const double* x, long n, long stride, int ncomp, double* part, double* out,
                       hipStream_t s);
 void launch_sum_virial(const double* wpart, long nblocks, double* out, hipStream_t s);

@@ -66,7 +66,7 @@ StaticLayout layout_for(const LevelOps& L, int n, long long npairs, bool need_ea
   StaticLayout s;
   size_t o = 0;
   s.part = o;
-  o += align_up(6 * kSumParts * sizeof(double));
+  o += align_up(7 * kSumParts * sizeof(double));
   s.flag = o;
   o += kAlign;
   s.eatom = o;

@@ -922,8 +922,15 @@ static int read_back(NbrWork* w, const int* flag, long long* total, int* flags, 
 // E = sum_k (bx_k + 2) / nb_k |H_k|, each carries a rounding error below 2^-24 E, so
 // |d2_32 - d2| < 2^-24 (7 r E + 3 r^2) for distances r near the cutoff; the margin is four times
 // that.
+// Brick shape: the least estimated time per centre atom.  A workgroup stages its halo (about
+// kStageWeight of a centre pass per staged atom and thread) and then runs ceil(centres /
+// kBrickThreads) passes of its lanes over the centres, each pass costing the same whatever the
+// number of lanes left busy; so bricks whose centres fit the lanes (with two standard deviations
+// to spare) avoid a nearly empty second pass (at 8.2 atoms per bin: 3x3x3 bins, 221 centres,
+// instead of 3x3x4, 295).
+constexpr double kStageWeight = 0.0143;
 static bool brick_shape(const int* nb, double per_bin, const double* H, double rcut, BrickArgs* ba) {
-  int best = 0;
+  double best = 0.0;
   for (int x = 1; x <= 8; ++x)
     for (int y = 1; y <= 8; ++y)
       for (int z = 1; z <= 8; ++z) {
@@ -931,8 +938,12 @@ static bool brick_shape(const int* nb, double per_bin, const double* H, double r
         const int halo = (x + 2) * (y + 2) * (z + 2), inner = x * y * z;
         if (halo > kMaxHalo || inner > kMaxInner) continue;
         if (halo * per_bin > (2.0 / 3.0) * kBrickMaxC) continue;
-        // prefer more centres per brick, then the more compact shape
-        const int score = inner * 64 - halo;
+        const double centres = std::max(inner * per_bin, 1e-9);
+        // passes for a brick two standard deviations above the mean count
+        const double passes = std::max(1.0, std::ceil((centres + 2.0 * std::sqrt(centres)) / kBrickThreads));
+        const double cost = (kStageWeight * halo * per_bin / kBrickThreads + passes) / centres;
+        // the cheapest per centre, then the more compact shape among equal costs
+        const double score = 1.0 / cost - 1e-9 * halo;
         if (score > best) {
           best = score;
           ba->bx[0] = x;
@@ -940,7 +951,7 @@ static bool brick_shape(const int* nb, double per_bin, const double* H, double r
           ba->bx[2] = z;
         }
       }
-  if (!best) return false;
+  if (best <= 0.0) return false;
   double ext = 0.0;
   for (int k = 0; k < 3; ++k) {
     ba->nbk[k] = (nb[k] + ba->bx[k] - 1) / ba->bx[k];

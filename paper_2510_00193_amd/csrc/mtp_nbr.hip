@@ -597,21 +597,32 @@ __global__ __launch_bounds__(kBrickThreads) void k_brick_rows(PlanArgs pa, Brick
     const bool small = __all(cnt <= 32);
     if (small) bitonic_sort<32>(v);
     else bitonic_sort<ROWCAP>(v);
+    // the row in registers (partners, packed images; the first 32 partner slots padded with
+    // INT_MAX, which k_rows_copy ranks against unmasked), then stored four slots per 16-byte
+    // store, as far as the row or the padded slots reach
     int* rj = rows_j + (long)i * cap;
     int* rs = rows_s + (long)i * cap;
+    int jv[ROWCAP], sv[ROWCAP];
     int m = 0;
 #pragma unroll
     for (int t = 0; t < ROWCAP; ++t) {
+      jv[t] = 0x7FFFFFFF;
+      sv[t] = 0;
       if ((t < 32 || !small) && v[t] != 0xFFFFFFFFu) {
         const unsigned u = mylist[(v[t] & 63u) * kBrickThreads];
         const long long key = ckey[u & 0x7FFF] + koff;
         const int n1 = (int)((key >> 16) & 0xFF) - 128, n2 = (int)((key >> 8) & 0xFF) - 128,
                   n3 = (int)(key & 0xFF) - 128;
-        rj[t] = (int)(key >> 24);
-        rs[t] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
+        jv[t] = (int)(key >> 24);
+        sv[t] = (n1 & 0xFF) | ((n2 & 0xFF) << 8) | ((n3 & 0xFF) << 16);
         ++m;
-      } else if (t < 32) {
-        rj[t] = 0x7FFFFFFF;  // pad the first 32 slots: k_rows_copy ranks against them unmasked
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < ROWCAP / 4; ++g) {
+      if (4 * g < 32 || 4 * g < m) {
+        reinterpret_cast<int4*>(rj)[g] = make_int4(jv[4 * g], jv[4 * g + 1], jv[4 * g + 2], jv[4 * g + 3]);
+        if (4 * g < m) reinterpret_cast<int4*>(rs)[g] = make_int4(sv[4 * g], sv[4 * g + 1], sv[4 * g + 2], sv[4 * g + 3]);
       }
     }
     counts[i] = m;

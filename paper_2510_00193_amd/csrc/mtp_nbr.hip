@@ -165,6 +165,29 @@ __global__ void k_batch_fill(const double* __restrict__ pos, const double* __res
 }
 
 // ---------------------------------------------------------------- cell path
+// counter[key] += 1 for every active lane, with one atomic per distinct key among the lanes of
+// the wave: the lowest remaining lane leads its key's lanes, adds their count, and each lane
+// gets the old value plus its rank among them in lane order.  (Atoms in index order mostly share
+// bins with their neighbours in the wave, so this replaces about eight atomics on one address
+// by one: the scatter into bins 72 -> 55 us at 1,024,000 atoms; the plain count, whose result
+// is unused, was not faster with it.)
+__device__ __forceinline__ int wave_counted_inc(int* counter, int key) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(1);
+  int result = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lkey = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(key == lkey) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[lkey], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if (key == lkey) result = base + __popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return result;
+}
+
 __global__ void k_bin(const double* __restrict__ pos, const int* __restrict__ species, int nsp, int n,
                       PlanArgs pa, int* __restrict__ bin, int* __restrict__ img,
                       int* __restrict__ bincount, int* __restrict__ flag) {
@@ -219,7 +242,7 @@ __global__ void k_bin_scatter(int n, const int* __restrict__ bin, const int* __r
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int id = bin[i];
-  const int q = binstart[id] + atomicAdd(&binfill[id], 1);
+  const int q = binstart[id] + wave_counted_inc(binfill, id);
   binatoms[q] = i;
   if (binpos) {
     binpos[3L * q] = pos[3 * i];

@@ -201,7 +201,9 @@ int mtp_grade_config(mtp_model* m, const mtp_system* sys, const mtp_nlist* nl, c
  *         all updated in place (rows exchanged, ainv kept as the inverse).
  *   swaps host [2 * max_swaps] or NULL: the (i, k) of every swap in order; grades host
  *         [max_swaps] or NULL: the signed (c_i A^-1)_k of every swap; *n_swaps (host) swaps done.
- * 1 <= n <= 4096.  Synchronizes once per iteration (the host decides whether to continue). */
+ * 1 <= n <= 4096.  Synchronizes once per iteration (the host decides whether to continue).
+ * Returns MTP_ERR_ARG for bad sizes or null matrices, and when the selected entry is not finite
+ * (NaN or infinite candidates or inverse): the swaps done before stay applied and counted. */
 int mtp_maxvol(mtp_model* m, double* cand, int n_cand, int n, double* active, double* ainv, double tol,
                int max_swaps, int* swaps, double* grades, int* n_swaps, void* stream);
 

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <cmath>
+
 #include <string>
 
 #include "mtp.h"
@@ -65,8 +67,11 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rowmax(const double* __restr
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (col < n) keep_max(best[r], bk[r], fabs(acc[r]), col);
+    for (int r = 0; r < 4; ++r) {
+      // a NaN product counts as the largest magnitude, so that it is selected and reported
+      const double v = fabs(acc[r]);
+      if (col < n) keep_max(best[r], bk[r], isnan(v) ? INFINITY : v, col);
+    }
   }
   // rows 4 r + kq: reduce over the 16 lanes that share kq (the columns)
 #pragma unroll
@@ -116,10 +121,12 @@ __global__ __launch_bounds__(kNT) void k_argmax_part(const double* __restrict__ 
   }
 }
 
-// out: [0] = row i, [1] = column k (as doubles), [2] = g = (c_i Ainv)_k (signed)
+// out: [0] = row i, [1] = column k (as doubles), [2] = g = (c_i Ainv)_k (signed).  Every row
+// holds a column in [0, n) (column 0 always competes), so i and k are in range; they are still
+// clamped, with g set to NaN, should that ever fail.
 __global__ __launch_bounds__(kNT) void k_argmax_final(const double* __restrict__ pv, const int* __restrict__ pi,
                                                       const int* __restrict__ rarg, const double* __restrict__ C,
-                                                      int n, const double* __restrict__ ainv,
+                                                      int m, int n, const double* __restrict__ ainv,
                                                       double* __restrict__ out) {
   __shared__ double sv[kNT];
   __shared__ int si[kNT];
@@ -140,11 +147,15 @@ __global__ __launch_bounds__(kNT) void k_argmax_final(const double* __restrict__
     }
     __syncthreads();
   }
-  const int i = si[0], k = rarg[i];
+  const bool i_ok = si[0] >= 0 && si[0] < m;
+  const int i = i_ok ? si[0] : 0;
+  const bool k_ok = i_ok && rarg[i] >= 0 && rarg[i] < n;
+  const int k = k_ok ? rarg[i] : 0;
   // signed g = sum_t C[i][t] Ainv[t][k], fixed-order tree over the threads
   double part = 0.0;
   for (int t = threadIdx.x; t < n; t += kNT) part = fma(C[(long)i * n + t], ainv[(long)t * n + k], part);
-  const double g = block_sum<kNT>(part, sg);
+  const double gs = block_sum<kNT>(part, sg);
+  const double g = k_ok ? gs : NAN;
   if (threadIdx.x == 0) {
     out[0] = (double)i;
     out[1] = (double)k;
@@ -209,11 +220,13 @@ extern "C" int mtp_maxvol(mtp_model* m, double* cand, int n_cand, int n, double*
     hipLaunchKernelGGL(k_rowmax, dim3((tiles + kRowWaves - 1) / kRowWaves), dim3(64 * kRowWaves), 0, s, cand,
                        n_cand, n, ainv, rmax, rarg);
     hipLaunchKernelGGL(k_argmax_part, dim3(kArgParts), dim3(kNT), 0, s, rmax, n_cand, pv, pi);
-    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(kNT), 0, s, pv, pi, rarg, cand, n, ainv, sel);
+    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(kNT), 0, s, pv, pi, rarg, cand, n_cand, n, ainv, sel);
     if (hipGetLastError() != hipSuccess) return mtp_fail(MTP_ERR_HIP, "mtp_maxvol: launch failed");
     if (hipMemcpyAsync(host, sel, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return mtp_fail(MTP_ERR_HIP, "mtp_maxvol: reading the selection failed");
+    if (!std::isfinite(host[2]))
+      return mtp_fail(MTP_ERR_ARG, "mtp_maxvol: non-finite grade (candidates or inverse not finite)");
     if (!(fabs(host[2]) > 1.0 + tol)) break;
     hipLaunchKernelGGL(k_swap, dim3(1), dim3(threads), 2 * n * sizeof(double), s, cand, active, ainv, n, sel);
     if (hipGetLastError() != hipSuccess) return mtp_fail(MTP_ERR_HIP, "mtp_maxvol: launch failed");

@@ -64,3 +64,24 @@ def test_maxvol_stops_at_once_when_grades_are_below_one():
     active = np.eye(n) + 0.2 * rng.normal(size=(n, n))
     cand = rng.uniform(-0.4, 0.4, size=(m, n)) @ active
     assert _run(pot, active, cand, 1e-3, 10, "below one") == []
+
+
+def test_maxvol_rejects_non_finite_candidates():
+    """A NaN or infinite candidate makes the selected entry non-finite: an error, no swap."""
+    from paper_2510_00193_amd._lib import MtpError
+    s, p = small_lattice(94, (2, 2, 2), 3.16, 0.05, 6, 1)
+    pot = _pot(p)
+    rng = np.random.default_rng(10)
+    n, m = 5, 20
+    active = np.eye(n) + 0.2 * rng.normal(size=(n, n))
+    for bad in (np.nan, np.inf):
+        cand = rng.normal(size=(m, n))
+        cand[7, 2] = bad
+        print(f"[maxvol non-finite] value={bad}", flush=True)
+        A = torch.as_tensor(active.copy(), device="cuda")
+        C = torch.as_tensor(cand, device="cuda")
+        Ai = torch.as_tensor(np.linalg.inv(active), device="cuda")
+        with pytest.raises(MtpError):
+            pot.maxvol(C, A, Ai, tol=1e-3, max_swaps=10)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(A.cpu().numpy(), active)

@@ -371,24 +371,40 @@ void launch_gather_forces(const int* off, const int* rev, const double* g, const
 }
 
 // Energy and virial of a small system in one workgroup: energy = sum_i ea[i] (n terms) and
-// virial[k] = sum_b wpart[6 b + k] (nb partials), each a fixed-order tree over the threads.
+// virial[k] = sum_b wpart[6 b + k] (nb partials).  Each thread sums a strided share of all seven
+// quantities, the waves reduce them with a butterfly, and thread 0 adds the waves' sums in
+// order (a fixed order throughout).
 __global__ __launch_bounds__(kSmallSumThreads) void k_sum_small(const double* __restrict__ ea, long n,
                                                                 const double* __restrict__ wpart, long nb,
                                                                 double* __restrict__ energy,
                                                                 double* __restrict__ virial) {
-  __shared__ double sh[kSmallSumThreads];
+  constexpr int kW = kSmallSumThreads / 64;
+  __shared__ double sh[kW][7];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   if (energy) {
-    double acc = 0.0;
-    for (long i = threadIdx.x; i < n; i += kSmallSumThreads) acc += ea[i];
-    const double v = block_sum<kSmallSumThreads>(acc, sh);
-    if (threadIdx.x == 0) energy[0] = v;
+#pragma unroll 4
+    for (long i = threadIdx.x; i < n; i += kSmallSumThreads) acc[0] += ea[i];
   }
-  if (virial) {
-    for (int k = 0; k < 6; ++k) {
-      double acc = 0.0;
-      for (long b = threadIdx.x; b < nb; b += kSmallSumThreads) acc += wpart[6 * b + k];
-      const double v = block_sum<kSmallSumThreads>(acc, sh);
-      if (threadIdx.x == 0) virial[k] = v;
+  if (virial)
+    for (long b = threadIdx.x; b < nb; b += kSmallSumThreads)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[1 + k] += wpart[6 * b + k];
+#pragma unroll
+  for (int c = 0; c < 7; ++c)
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) acc[c] += __shfl_xor(acc[c], s, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) sh[wave][c] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    double v = 0.0;
+    for (int w = 0; w < kW; ++w) v += sh[w][threadIdx.x];
+    if (threadIdx.x == 0) {
+      if (energy) energy[0] = v;
+    } else if (virial) {
+      virial[threadIdx.x - 1] = v;
     }
   }
 }

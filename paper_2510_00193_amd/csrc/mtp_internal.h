@@ -122,7 +122,7 @@ constexpr int kSumParts = 256;
 // energy (ea over n atoms) and virial (nb per-workgroup partials) of a small system in one
 // launch; either output may be null.  For n and nb up to kSmallSumMax.
 constexpr int kSmallSumThreads = 1024;
-constexpr long kSmallSumMax = 8192;
+constexpr long kSmallSumMax = 32768;
 void launch_sum_small(const double* ea, long n, const double* wpart, long nb, double* energy, double* virial,
                       hipStream_t s);
 // launch_sum_parts over two arrays in one pair of launches (part: (nc1 + nc2) * kSumParts

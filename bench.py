@@ -233,7 +233,8 @@ def section_adjoint(steps):
 
 def section_small(reps=200):
     """Small systems: latency of one E/F/virial evaluation of the 128-atom level-10 workload
-    (prebuilt list, synchronized per call), and the throughput of the 16,000-atom level-16
+    (prebuilt list, synchronized per call; also as a captured graph of the allocation-free
+    entry point, replayed), and the throughput of the 16,000-atom level-16
     two-species workload (prebuilt list) with the library's lanes-per-atom choice and with each
     setting forced."""
     import torch
@@ -256,9 +257,29 @@ def section_small(reps=200):
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
     dt = _timeit(lambda: pot.compute(pos, sp, s.cell, nlist=nl), reps)
+    # the same evaluation captured once (the allocation-free entry point) and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pot.compute_static(pos, sp, s.cell, nl)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pot.compute_static(pos, sp, s.cell, nl)
+    for _ in range(10):
+        graph.replay()
+    torch.cuda.synchronize()
+    glat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        glat.append(time.perf_counter() - t0)
     out["bcc-4x4x4-L10"] = {"atoms": s.n_atoms, "latency_us_median": float(np.median(lat) * 1e6),
                             "latency_us_best": float(np.min(lat) * 1e6),
-                            "pipelined_us_per_eval": dt * 1e6}
+                            "pipelined_us_per_eval": dt * 1e6,
+                            "graph_replay_latency_us_median": float(np.median(glat) * 1e6)}
     info = level_info(16)
     w = wl.workload(2, info["n_alpha"], info["n_mu"])
     (s,) = w["structures"]

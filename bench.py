@@ -346,7 +346,16 @@ def section_batch(steps, plain_sample=128):
             p1.param_grad(ps, ss, cell, 2.0 * float(energies[k] - e0_host[k]), fb.contiguous(), nlist=nl)
 
     dt_plain = _timeit(plain_pass, 1)
-    return {"value": len(structs) / dt, "unit": "configs/s", "ms_per_step": dt * 1e3,
+    # flops by the model: forward and backward of every pair and atom, and the parameter
+    # adjoint estimated at 2.5 times that work (its tangent passes over the same program)
+    fm = flop_model(info, params.n_cheb)
+    n_pairs = b.sizes()["n_pairs"]
+    fwd_bwd = n_pairs * (fm["moments"][1] + fm["pair_backward"][1]) + int(off[-1]) * fm["program"][1]
+    model = 3.5 * fwd_bwd
+    flops = {"forward_backward_gflop": fwd_bwd / 1e9, "with_adjoint_gflop": model / 1e9,
+             "tflops": model / dt / 1e12, "frac_fp64": model / dt / 1e12 / PEAK_FP64_TFLOPS,
+             "adjoint_model": "2.5 x forward + backward"}
+    return {"value": len(structs) / dt, "unit": "configs/s", "ms_per_step": dt * 1e3, "flop_model": flops,
             "atoms": int(off[-1]), "pairs": b.sizes()["n_pairs"], "schedule": choice,
             "plain": {"value": len(sample) / dt_plain, "unit": "configs/s", "sample_configs": len(sample),
                       "method": "mtp_compute + mtp_param_grad per configuration, prebuilt lists, one host "

@@ -660,19 +660,30 @@ __global__ __launch_bounds__(kBrickThreads) void k_brick_rows(PlanArgs pa, Brick
 // The wave counts cooperatively: in step v of entry slot e, the eight lanes 8k..8k+7 read the
 // eight 16-byte pieces of the first 32 slots of the row of lane 8(v % 8) + k's entry e (one
 // 128-byte line per eight lanes instead of a line per lane), count the entries below that
-// lane's i and sum over the eight lanes.  All exchanges and loads of a lane are issued before
+// lane's i and sum over the eight lanes; one exchange at the end hands each lane its count (lane
+// 8k + m keeps step m's sum).  All exchanges and loads of a lane are issued before
 // the first count, so a wave has every load of its rows in flight at once.  A row with all of
 // its first 32 entries below i continues alone, four entries at a time, up to counts[j].
 constexpr int kCsrThreads = 256;
-template <int CAP, int E>
+// sum over the eight lanes 8k..8k+7 with DPP lane exchanges (quads, then half-rows); every lane
+// of the eight ends with the same sum
+__device__ __forceinline__ int sum8(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  return v;
+}
+
+// i_lane0: the row of lane 0 of the wave; G lanes per row, so lane s's row is i_lane0 + s / G
+template <int CAP, int E, int G>
 __device__ __forceinline__ void mirror_rank(const int* __restrict__ rows_j, const int* __restrict__ counts,
-                                            int i, const int (&j)[E], int (&rank)[E]) {
+                                            int i, int i_lane0, const int (&j)[E], int (&rank)[E]) {
   const int l = threadIdx.x & 63;
   int js[E][8], is[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int src = 8 * v + (l >> 3);
-    is[v] = __shfl(i, src, 64);
+    is[v] = i_lane0 + src / G;
 #pragma unroll
     for (int e = 0; e < E; ++e) js[e][v] = __shfl(j[e], src, 64);
   }
@@ -684,18 +695,15 @@ __device__ __forceinline__ void mirror_rank(const int* __restrict__ rows_j, cons
       q[e][v] = reinterpret_cast<const int4*>(rows_j + (long)max(js[e][v], 0) * CAP)[l & 7];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    rank[e] = 0;
+    int mine = 0;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int x = is[v];
       const int4 w = q[e][v];
-      int part = js[e][v] >= 0 ? (w.x < x) + (w.y < x) + (w.z < x) + (w.w < x) : 0;
-      part += __shfl_xor(part, 1, 64);
-      part += __shfl_xor(part, 2, 64);
-      part += __shfl_xor(part, 4, 64);
-      const int got = __shfl(part, 8 * (l & 7), 64);
-      if ((l >> 3) == v) rank[e] = got;
+      const int part = sum8(js[e][v] >= 0 ? (w.x < x) + (w.y < x) + (w.z < x) + (w.w < x) : 0);
+      if ((l & 7) == v) mine = part;
     }
+    rank[e] = __shfl(mine, 8 * (l & 7) + (l >> 3), 64);
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -737,7 +745,7 @@ __global__ __launch_bounds__(kCsrThreads) void k_rows_copy(int n, const int* __r
     if (rev) {
 #pragma unroll
       for (int e = 0; e < E; ++e) oj[e] = off[max(j[e], 0)];
-      mirror_rank<CAP, E>(rows_j, counts, i, j, rank);
+      mirror_rank<CAP, E, G>(rows_j, counts, i, b * R + (int)(threadIdx.x & ~63u) / G, j, rank);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -59,6 +59,15 @@ def _ngroups(lv):
     return len(g) + 1 if isinstance(g, tuple) else g
 
 
+def _nrtparts(lv):
+    """Number of reverse-tangent parts of a generated level (read from its program header)."""
+    with open(os.path.join(GEN, f"mtp_L{lv}.inc")) as fh:
+        for line in fh:
+            if "static constexpr int NRTPART" in line:
+                return int(line.split("=")[1].strip().rstrip(";"))
+    raise RuntimeError(f"level {lv}: no NRTPART in the generated program")
+
+
 def _assembly(lv):
     """Translation unit that assembles the launcher table of one level."""
     fp32 = lv in FP32_LEVELS
@@ -69,7 +78,7 @@ def _assembly(lv):
     lines.append(f"AdjOps adj_ops_{lv}();")
     lines.append(f"void adj_fwd_{lv}(const SysArgs&, const double*, const double*, long, int, int, const double*, "
                  "double, double*, double*, hipStream_t);")
-    for g in range(_ngroups(lv)):
+    for g in range(_nrtparts(lv)):
         lines.append(f"void adj_rev_{lv}_{g}(const double*, const double*, long, int, const double*, "
                      "const double*, double*, hipStream_t);")
     lines += [f"LevelOps level_ops_{lv}() {{", "  LevelOps o{};", f"  using L = Lv{lv};",
@@ -80,7 +89,7 @@ def _assembly(lv):
         lines.append(f"  o.chain[1] = chain_ops_{lv}_f32();")
     lines.append(f"  o.adj = adj_ops_{lv}();")
     lines.append(f"  o.adj.tan_forward = &adj_fwd_{lv};")
-    for g in range(_ngroups(lv)):
+    for g in range(_nrtparts(lv)):
         lines.append(f"  o.adj.tan_reverse[{g}] = &adj_rev_{lv}_{g};")
     lines += ["  return o;", "}", "}  // namespace mtp", ""]
     return f"// Generated: launcher table of level {lv}.\n" + "\n".join(lines)
@@ -93,7 +102,7 @@ def level_units(lv):
              (f"mtp_L{lv}_b64.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, double, true, b64)")),
              (f"mtp_L{lv}_adj.hip", _unit(lv, f"MTP_DEFINE_ADJ(Lv{lv}, {lv})")),
              (f"mtp_L{lv}_tfw.hip", _unit(lv, f"MTP_DEFINE_ADJ_FWD(Lv{lv}, {lv})"))]
-    for g in range(_ngroups(lv)):
+    for g in range(_nrtparts(lv)):
         units.append((f"mtp_L{lv}_rev{g}.hip", _unit(lv, f"MTP_DEFINE_ADJ_REV(Lv{lv}, {lv}, {g})")))
     if lv in FP32_LEVELS:
         units.append((f"mtp_L{lv}_f32.hip", _unit(lv, f"MTP_DEFINE_CHAIN(Lv{lv}, {lv}, float, false, f32)")))
@@ -105,8 +114,14 @@ def generate(levels):
     os.makedirs(GEN, exist_ok=True)
     for lv in levels:
         write_level(lv, GEN, LEVELS[lv])
-        for name, text in level_units(lv):
+        units = level_units(lv)
+        for name, text in units:
             _write_if_changed(os.path.join(GEN, name), text)
+        # reverse-tangent units of an earlier, finer cut of the program
+        keep = {name for name, _ in units}
+        for name in os.listdir(GEN):
+            if name.startswith(f"mtp_L{lv}_rev") and name.endswith(".hip") and name not in keep:
+                os.remove(os.path.join(GEN, name))
     _write_if_changed(os.path.join(GEN, "levels.inc"),
                       "".join(f"MTP_LEVEL({lv})\n" for lv in levels))
 

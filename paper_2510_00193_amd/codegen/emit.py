@@ -299,6 +299,15 @@ PREFETCH_DEPTH = int(os.environ.get("MTP_PREFETCH_DEPTH", "24"))
 # the contraction adjoints with their tangents)
 TAN_PREFETCH_DEPTH = int(os.environ.get("MTP_TAN_PREFETCH_DEPTH", "24"))
 
+# Register estimate (VGPRs) of the reverse tangent of one block: values, tangents, adjoints and
+# adjoint tangents of its temporaries, plus the prefetched loads.  A part of the reverse-tangent
+# program holds the accumulators of its entries (two VGPRs each) next to its largest block;
+# parts are cut so that this stays within RTAN_REG_BUDGET (the 512 VGPR + AGPR of one wave per
+# SIMD, measured to spill little at this estimate).
+RTAN_REG_BUDGET = int(os.environ.get("MTP_RTAN_BUDGET", "512"))
+# blocks tried for each addition to a part (those adding the fewest new entries)
+RTAN_CANDIDATES = 12
+
 
 def _locality_order(blocks):
     """Contraction blocks reordered so that consecutive blocks share moment entries (each next
@@ -486,7 +495,7 @@ def _emit_dispatchers(w: _W, n_groups: int):
         w("}")
 
 
-def emit_level(level: int, n_groups: int = 1) -> str:
+def emit_level(level: int, n_groups: int = 1, rtan_budget: int = RTAN_REG_BUDGET) -> str:
     prog = build_program(level)
     groups = entry_groups(prog, n_groups)
     agroups = adj_entry_groups(prog)
@@ -513,6 +522,9 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     w("static constexpr int AMU_HI[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[1] - 1][0]) for g in agroups) + "};")
     # ranges of the moment-tangent kernel
     tgroups = tangent_moment_groups(groups, agroups)
+    rparts = rev_tan_parts(prog, rtan_budget)
+    # parts of the reverse-tangent program, run in order (one kernel each)
+    w(f"static constexpr int NRTPART = {len(rparts)};")
     w(f"static constexpr int NTGROUP = {len(tgroups)};")
     w("static constexpr int TGROUP_LO[NTGROUP] = {" + ", ".join(str(g[0]) for g in tgroups) + "};")
     w("static constexpr int TGROUP_HI[NTGROUP] = {" + ", ".join(str(g[1]) for g in tgroups) + "};")
@@ -526,7 +538,7 @@ def emit_level(level: int, n_groups: int = 1) -> str:
     _emit_components_reverse(w, prog, groups)
     _emit_products(w, prog)
     _emit_dispatchers(w, len(groups))
-    emit_tangent_parts(w, prog, groups, agroups)
+    emit_tangent_parts(w, prog, groups, agroups, rparts)
     w.pop()
     w("};")
     return w.text()
@@ -724,17 +736,21 @@ def _emit_components_forward_tangent(w: _W, prog: Program):
     w("}")
 
 
-def _adj2(ref, lo, hi):
-    """(adjoint, adjoint tangent) names of a reference inside a reverse-tangent block."""
+def _adj2(ref, slot):
+    """(adjoint, adjoint tangent) names of a reference inside a reverse-tangent block; slot maps
+    the moment entries accumulated by the part to their register index."""
     kind, k = ref
     if kind == "t":
         return f"tb{k}", f"tbd{k}"
     if kind == "m":
-        return (None, f"mbd[{k - lo}]") if lo <= k < hi else (None, None)
+        return (None, f"mbd[{slot[k]}]") if k in slot else (None, None)
     return "cb", "cbd"
 
 
-def _emit_block_reverse_tangent(w: _W, blk, lo, hi):
+def _emit_block_reverse_tangent(w: _W, blk, slot, flush=None):
+    """The block read backwards.  flush maps moment entries to the line that stores their
+    accumulated adjoint tangent; each such line is emitted right after the entry's last update
+    in the block, so its register is free for the rest of the block."""
     rev_ops = list(reversed(blk.ops))
     seen_dst = []
     by_dst = defaultdict(list)
@@ -742,70 +758,163 @@ def _emit_block_reverse_tangent(w: _W, blk, lo, hi):
         if dst not in by_dst:
             seen_dst.append(dst)
         by_dst[dst].append((x, y, wgt))
+    items = []  # (lines, moment entry updated or None)
     for dst in seen_dst:
         lst = by_dst[dst]
-        db, dbd = _adj2(dst, lo, hi)
+        db, dbd = _adj2(dst, slot)
         if lst[0][1] is None:
             (x, _, _), = lst
-            xb, xbd = _adj2(x, lo, hi)
+            xb, xbd = _adj2(x, slot)
+            lines = []
             if xb:
-                w(f"{xb} += {db};")
+                lines.append(f"{xb} += {db};")
             if xbd:
-                w(f"{xbd} += {dbd};")
+                lines.append(f"{xbd} += {dbd};")
+            items.append((lines, x[1] if x[0] == "m" and xbd else None))
             continue
         xs, ys = {}, {}
         for x, y, wgt in lst:
             xs.setdefault(x, []).append((y, wgt))
             ys.setdefault(y, []).append((x, wgt))
         for x, l2 in xs.items():
-            xb, xbd = _adj2(x, lo, hi)
+            xb, xbd = _adj2(x, slot)
             if not xb and not xbd:
                 continue
-            _emit_inner2(w, l2)
+            sub = _W()
+            _emit_inner2(sub, l2)
             if xb:
-                w(f"  {xb} = fma({db}, s, {xb});")
-            w(f"  {xbd} = fma({dbd}, s, fma({db}, sd, {xbd})); }}")
+                sub(f"  {xb} = fma({db}, s, {xb});")
+            sub(f"  {xbd} = fma({dbd}, s, fma({db}, sd, {xbd})); }}")
+            items.append((sub.lines, x[1] if x[0] == "m" else None))
         for y, l2 in ys.items():
-            yb, ybd = _adj2(y, lo, hi)
+            yb, ybd = _adj2(y, slot)
             if not ybd:
                 continue
-            _emit_inner2(w, l2)
-            w(f"  {ybd} = fma({dbd}, s, fma({db}, sd, {ybd})); }}")
+            sub = _W()
+            _emit_inner2(sub, l2)
+            sub(f"  {ybd} = fma({dbd}, s, fma({db}, sd, {ybd})); }}")
+            items.append((sub.lines, y[1] if y[0] == "m" else None))
+    flush = dict(flush or {})
+    last = {e: i for i, (_, e) in enumerate(items) if e is not None}
+    for i, (lines, e) in enumerate(items):
+        for line in lines:
+            w(line)
+        if e is not None and last[e] == i and e in flush:
+            w(flush.pop(e))
+    for line in flush.values():
+        w(line)
 
 
-def _emit_components_reverse_tangent(w: _W, prog: Program, groups):
-    for gi, (lo, hi) in enumerate(groups):
-        w("template <class R, class MA, class CB>")
-        w(f"static __device__ __forceinline__ void rev_tan_g{gi}(const MA& M, const MA& Md, const CB& Cb,")
-        w("    const CB& Cbd, R* __restrict__ mbd) {")
+def _rtan_peak(blk):
+    return 8 * blk.n_temp + 4 * len(blk.entries) + 48
+
+
+def _rtan_live(order):
+    """Register estimate of a part whose blocks run in the given order: an entry's accumulator
+    lives from the first block of the part that touches it to the last one (it is stored right
+    after that block), next to the block's own need."""
+    first, last = {}, {}
+    for i, b in enumerate(order):
+        for e in b.entries:
+            first.setdefault(e, i)
+            last[e] = i
+    starts, ends = defaultdict(int), defaultdict(int)
+    for e in first:
+        starts[first[e]] += 1
+        ends[last[e]] += 1
+    live = worst = 0
+    for i, b in enumerate(order):
+        live += starts[i]
+        worst = max(worst, 2 * live + _rtan_peak(b))
+        live -= ends[i]
+    return worst
+
+
+def rev_tan_parts(prog: Program, budget=RTAN_REG_BUDGET):
+    """Contraction blocks of the reverse-tangent program cut into parts (one kernel each).  A
+    part starts from the remaining block with the largest register need and takes, while the
+    estimate of the part in locality order fits the budget, the block that adds the fewest new
+    moment entries (among the closest few candidates).  Returns the parts as lists of blocks
+    in locality order."""
+    rem = sorted(prog.blocks, key=lambda b: b.q)
+    parts = []
+    while rem:
+        b0 = max(rem, key=lambda b: (_rtan_peak(b), len(b.ops), -b.q))
+        rem.remove(b0)
+        cur, es = [b0], set(b0.entries)
+        while rem:
+            cand = sorted(rem, key=lambda b: (len(set(b.entries) - es), -len(b.ops), b.q))[:RTAN_CANDIDATES]
+            nb = next((b for b in cand if _rtan_live(_locality_order(cur + [b])) <= budget), None)
+            if nb is None:
+                break
+            cur.append(nb)
+            rem.remove(nb)
+            es |= set(nb.entries)
+        parts.append(_locality_order(cur))
+    return parts
+
+
+def _emit_components_reverse_tangent(w: _W, prog: Program, parts):
+    """One function per part: the forward tangent of each of its blocks again, then the block
+    read backwards, accumulating the tangents of the moment adjoints of the entries the part
+    touches.  The part that touches an entry first stores it, later parts add to it, and the
+    first part stores zero for entries no block reads, so running the parts in order leaves
+    out[e * ld] = d(mbar_e) for every entry."""
+    first = {}
+    for pi, part in enumerate(parts):
+        for blk in part:
+            for e in blk.entries:
+                first.setdefault(e, pi)
+    for pi, part in enumerate(parts):
+        entries = sorted(set(e for b in part for e in b.entries))
+        slot = {e: k for k, e in enumerate(entries)}
+        w("template <class R, class MA, class CB, class OUT>")
+        w(f"static __device__ __forceinline__ void rev_tan_p{pi}(const MA& M, const MA& Md, const CB& Cb,")
+        w("    const CB& Cbd, const OUT& out, long ld) {")
         w.push()
-        blocks = _locality_order([b for b in prog.blocks if any(lo <= e < hi for e in b.entries)])
+        last = {}
+        for bi, blk in enumerate(part):
+            for e in blk.entries:
+                last[e] = bi
+        started = set()
+        w(f"R mbd[{len(entries)}];")
         # every load of the program in order (moments, their tangents, then the block's adjoint
         # pair), kept TAN_PREFETCH_DEPTH ahead across the fenced blocks
         seq = []
-        for blk in blocks:
+        for blk in part:
             seq += [(f"me{e}", f"M({e})") for e in blk.entries] + [(f"mde{e}", f"Md({e})") for e in blk.entries]
             seq += [("cb", f"Cb[{blk.q}]"), ("cbd", f"Cbd[{blk.q}]")]
         depth = max(1, min(TAN_PREFETCH_DEPTH, len(seq)))
         for k in range(depth):
             w(f"R pf{k} = {seq[k][1]};")
         pos = 0
-        for blk in blocks:
+        for bi, blk in enumerate(part):
             w(f"{{  // contraction {blk.q}")
             w.push()
             w("MTP_BLOCK_FENCE();")
             for _ in range(2 * len(blk.entries) + 2):
-                slot = pos % depth
-                w(f"const R {seq[pos][0]} = pf{slot};")
+                sl = pos % depth
+                w(f"const R {seq[pos][0]} = pf{sl};")
                 if pos + depth < len(seq):
-                    w(f"pf{slot} = {seq[pos + depth][1]};")
+                    w(f"pf{sl} = {seq[pos + depth][1]};")
                 pos += 1
+            for e in blk.entries:
+                if e not in started:
+                    started.add(e)
+                    w(f"mbd[{slot[e]}] = R(0);")
             _emit_block_forward_tangent(w, blk, with_output=False)
             for k in range(blk.n_temp):
                 w(f"R tb{k} = R(0), tbd{k} = R(0);")
-            _emit_block_reverse_tangent(w, blk, lo, hi)
+            # entries the part touches for the last time here are stored after their last update
+            flush = {e: f"out[{e} * ld] {'=' if first[e] == pi else '+='} double(mbd[{slot[e]}]);"
+                     for e in blk.entries if last[e] == bi}
+            _emit_block_reverse_tangent(w, blk, slot, flush)
             w.pop()
             w("}")
+        if pi == 0:
+            for e in range(prog.n_mom):
+                if e not in first:
+                    w(f"out[{e} * ld] = 0.0;")
         w.pop()
         w("}")
 
@@ -861,23 +970,25 @@ def _emit_products_tangent(w: _W, prog: Program):
     w("}")
 
 
-def _emit_tangent_dispatchers(w: _W, n_groups: int, n_agroups: int, n_tgroups: int):
+def _emit_tangent_dispatchers(w: _W, n_rtparts: int, n_agroups: int, n_tgroups: int):
     sigs = (
         ("tan_moments", "R* __restrict__ md, const R* __restrict__ f, const R* __restrict__ fp, R x, R y, R z, "
                         "R ex, R ey, R ez, R rdot", "md, f, fp, x, y, z, ex, ey, ez, rdot", "class R", "<R>"),
         ("adj_pair", "const R* __restrict__ mb, const R* __restrict__ mbd, R x, R y, R z, R ex, R ey, R ez, "
                      "R* __restrict__ S, R* __restrict__ A", "mb, mbd, x, y, z, ex, ey, ez, S, A", "class R", "<R>"),
         ("rev_tan", "const MA& M, const MA& Md, const CB& Cb, const CB& Cbd, "
-                    "R* __restrict__ mbd", "M, Md, Cb, Cbd, mbd", "class R, class MA, class CB", "<R, MA, CB>"),
+                    "const OUT& out, long ld", "M, Md, Cb, Cbd, out, ld", "class R, class MA, class CB, class OUT",
+         "<R, MA, CB>"),
     )
     for name, params, args, tparams, targs in sigs:
         w(f"template <int G, {tparams}>")
         w(f"static __device__ __forceinline__ void {name}({params}) {{")
         w.push()
-        count = {"adj_pair": n_agroups, "tan_moments": n_tgroups}.get(name, n_groups)
+        count = {"adj_pair": n_agroups, "tan_moments": n_tgroups, "rev_tan": n_rtparts}[name]
+        tag = "p" if name == "rev_tan" else "g"
         for g in range(count):
             kw = "if constexpr" if g == 0 else "else if constexpr"
-            w(f"{kw} (G == {g}) {name}_g{g}{targs}({args});")
+            w(f"{kw} (G == {g}) {name}_{tag}{g}{targs}({args});")
         w.pop()
         w("}")
 
@@ -889,11 +1000,11 @@ def tangent_moment_groups(groups, agroups):
     return agroups if len(groups) == 1 else groups
 
 
-def emit_tangent_parts(w: _W, prog: Program, groups, agroups):
+def emit_tangent_parts(w: _W, prog: Program, groups, agroups, rparts):
     tgroups = tangent_moment_groups(groups, agroups)
     _emit_tangent_pair_functions(w, prog, tgroups)
     _emit_adj_pair_functions(w, prog, agroups)
     _emit_components_forward_tangent(w, prog)
-    _emit_components_reverse_tangent(w, prog, groups)
+    _emit_components_reverse_tangent(w, prog, rparts)
     _emit_products_tangent(w, prog)
-    _emit_tangent_dispatchers(w, len(groups), len(agroups), len(tgroups))
+    _emit_tangent_dispatchers(w, len(rparts), len(agroups), len(tgroups))

@@ -712,7 +712,7 @@ extern "C" int mtp_param_grad(mtp_model* m, const mtp_system* sys, const mtp_nli
       ProfScope ps(&m->prof, P_TANGENT, s);
       L.adj.tan_forward(a, mom, mdot, ld, i0, cn, (const double*)m->linear.p, ebar, xout, cbard, s);
     }
-    for (int g = 0; g < L.ngroup; ++g) {
+    for (int g = 0; g < L.adj.nrtpart; ++g) {
       ProfScope ps(&m->prof, P_TANGENT, s);
       L.adj.tan_reverse[g](mom, mdot, ld, cn, cbar, cbard, mbard, s);
     }

@@ -272,7 +272,7 @@ static void run_impl(mtp_batch* b, const double* e_target, const double* f_targe
       L.adj.tan_forward(a, (const double*)b->mom.p, (const double*)b->mdot.p, ld, (int)i0, cn,
                     (const double*)m->linear.p, 0.0, (double*)b->xout.p, (double*)b->cbard.p, s);
     }
-    for (int gi = 0; gi < L.ngroup; ++gi) {
+    for (int gi = 0; gi < L.adj.nrtpart; ++gi) {
       ProfScope ps(&m->prof, P_TANGENT, s);
       L.adj.tan_reverse[gi]((const double*)b->mom.p, (const double*)b->mdot.p, ld, cn, (const double*)b->cbar.p,
                     (const double*)b->cbard.p, (double*)b->mbard.p, s);

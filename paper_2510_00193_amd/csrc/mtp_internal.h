@@ -7,6 +7,7 @@ namespace mtp {
 constexpr int kMaxSpecies = 8;
 constexpr int kMaxMu = 8;
 constexpr int kMaxGroups = 4;    // moment groups per level
+constexpr int kMaxRevParts = 16;  // parts of the reverse-tangent program per level
 constexpr int kMaxRadial = 1024;  // doubles of the staged c[z_i][z_j][mu][b] table
 constexpr int kMaxChebHost = 16;
 
@@ -61,9 +62,11 @@ struct AdjOps {
                       long ld, hipStream_t s);
   void (*tan_forward)(const SysArgs& a, const double* m, const double* md, long ld, int i0, int n,
                       const double* xi, double ebar, double* out, double* cbard, hipStream_t s);
-  // one launcher per moment group (compiled in separate units)
-  void (*tan_reverse[kMaxGroups])(const double* m, const double* md, long ld, int n, const double* cb,
-                                  const double* cbd, double* mbd, hipStream_t s);
+  // one launcher per part of the reverse-tangent program (compiled in separate units); the
+  // parts store or add their entries of mbd and run in order 0 .. nrtpart - 1 on one stream
+  void (*tan_reverse[kMaxRevParts])(const double* m, const double* md, long ld, int n, const double* cb,
+                                    const double* cbd, double* mbd, hipStream_t s);
+  int nrtpart;
   // grp is one of the nagroup adjoint groups (moment ranges sized for the pair kernel's
   // registers, independent of the chain's groups)
   void (*adj_pairs)(int grp, const SysArgs& a, const double* fbar, int i0, int n, const double* mb,

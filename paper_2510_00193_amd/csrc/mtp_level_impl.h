@@ -74,9 +74,27 @@ __device__ __forceinline__ R group_sum(R v) {
 
 inline int pair_grid(const SysArgs& a, int nb) { return a.queue ? std::max(1, std::min(nb, a.pgrid)) : nb; }
 
-// Accessor of a moment vector held in global memory in [entry][atom] layout.
+// Accessors of [row][atom] arrays in global memory.  The address of a row is the same for the
+// whole wave (scalar registers) and each lane adds its byte offset, so a load takes the
+// scalar-base form: no per-row 64-bit address is kept in vector registers (the compiler
+// otherwise precomputes the addresses of every row a program reads and spills them).
+__device__ __forceinline__ unsigned lane_bytes(int li, int size) { return (unsigned)li * (unsigned)size; }
+
+// Moment vector of a lane, [entry][atom] layout.
 template <class R>
 struct GlobalMoments {
+  const R* __restrict__ base;
+  long ld;
+  unsigned off;  // byte offset of the lane's atom in a row
+  __device__ __forceinline__ R operator()(int e) const {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base + (long)e * ld) + off);
+  }
+};
+
+// The same with a per-lane 64-bit pointer (vector addresses): measured faster for the forward
+// program kernels (k_program, k_program_fwd), whose few spills do not come from addresses.
+template <class R>
+struct LaneMoments {
   const R* __restrict__ p;
   long ld;
   __device__ __forceinline__ R operator()(int e) const { return p[(long)e * ld]; }
@@ -85,9 +103,22 @@ struct GlobalMoments {
 // Per-lane vector read from a [component][atom] array in global memory, one load per use.
 template <class R>
 struct GlobalVector {
-  const R* __restrict__ p;
+  const R* __restrict__ base;
   long ld;
-  __device__ __forceinline__ R operator[](int q) const { return p[(long)q * ld]; }
+  unsigned off;
+  __device__ __forceinline__ R operator[](int q) const {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base + (long)q * ld) + off);
+  }
+};
+
+// Per-lane element i of a [row][atom] array written in place (i = row * ld).
+template <class R>
+struct LaneRows {
+  R* __restrict__ base;
+  unsigned off;
+  __device__ __forceinline__ R& operator[](long i) const {
+    return *reinterpret_cast<R*>(reinterpret_cast<char*>(base + i) + off);
+  }
 };
 
 // Contraction-adjoint vectors longer than this are read from memory where a block needs them
@@ -223,7 +254,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_fwd(const R* __restrict_
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  GlobalMoments<R> M{mom + li, ld};
+  LaneMoments<R> M{mom + li, ld};
   R C[L::NCOMP];
   L::template fwd<R>(M, C);
   R Cb[L::NCOMP];
@@ -244,12 +275,12 @@ __global__ __launch_bounds__(kLaneBlock) void k_program_rev(const R* __restrict_
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
   constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
-  GlobalMoments<R> M{mom + li, ld};
+  GlobalMoments<R> M{mom, ld, lane_bytes(li, sizeof(R))};
   R mb[NG];
 #pragma unroll
   for (int e = 0; e < NG; ++e) mb[e] = R(0);
   if constexpr (L::NCOMP > kRegComps) {
-    L::template rev<G>(M, GlobalVector<R>{cbar + li, ld}, mb);
+    L::template rev<G>(M, GlobalVector<R>{cbar, ld, lane_bytes(li, sizeof(R))}, mb);
   } else {
     R Cb[L::NCOMP];
 #pragma unroll
@@ -276,7 +307,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_program(const R* __restrict__ mo
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  GlobalMoments<R> M{mom + li, ld};
+  LaneMoments<R> M{mom + li, ld};
   {
     R C[L::NCOMP], Cb[L::NCOMP];
     L::template fwd<R>(M, C);
@@ -446,7 +477,8 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_forward(const double* __rest
     const int i = perm ? perm[i0 + li] : i0 + li;
     ebar = ebar_cfg[cfg ? cfg[i] : 0];
   }
-  GlobalMoments<double> M{mom + li, ld}, Md{mdot + li, ld};
+  const unsigned lo = lane_bytes(li, sizeof(double));
+  GlobalMoments<double> M{mom, ld, lo}, Md{mdot, ld, lo};
   double C[L::NCOMP], Cd[L::NCOMP];
   L::template fwd_tan<double>(M, Md, C, Cd);
   double Cb[L::NCOMP], Cbd[L::NCOMP];
@@ -455,8 +487,10 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_forward(const double* __rest
   for (int q = 0; q < L::NCOMP; ++q) cbard[(long)q * ld + li] = Cbd[q];
 }
 
-// Tangent of the moment adjoint: mbd = d(mbar) along the moment tangent.
-template <class L, int G>
+// Tangent of the moment adjoint: mbd = d(mbar) along the moment tangent.  The reverse program
+// is cut into parts of contraction blocks sized for the registers; part P stores or adds the
+// entries it touches, so the parts run in order 0, 1, ... on one stream.
+template <class L, int P>
 __global__ __launch_bounds__(kLaneBlock) void k_tan_reverse(const double* __restrict__ mom,
                                                             const double* __restrict__ mdot, long ld,
                                                             int n, const double* __restrict__ cbar,
@@ -465,13 +499,11 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_reverse(const double* __rest
   const int b = xcd_logical_block(blockIdx.x, gridDim.x);
   const int li = b * kLaneBlock + threadIdx.x;
   if (li >= n) return;
-  constexpr int LO = L::GROUP_LO[G], HI = L::GROUP_HI[G], NG = HI - LO;
-  GlobalMoments<double> M{mom + li, ld}, Md{mdot + li, ld};
-  double mbd[NG];
-#pragma unroll
-  for (int e = 0; e < NG; ++e) mbd[e] = 0.0;
+  const unsigned lo = lane_bytes(li, sizeof(double));
+  GlobalMoments<double> M{mom, ld, lo}, Md{mdot, ld, lo};
   if constexpr (L::NCOMP > kRegComps) {
-    L::template rev_tan<G>(M, Md, GlobalVector<double>{cbar + li, ld}, GlobalVector<double>{cbard + li, ld}, mbd);
+    L::template rev_tan<P, double>(M, Md, GlobalVector<double>{cbar, ld, lo}, GlobalVector<double>{cbard, ld, lo},
+                                   LaneRows<double>{mbard, lo}, ld);
   } else {
     double Cb[L::NCOMP], Cbd[L::NCOMP];
 #pragma unroll
@@ -479,10 +511,8 @@ __global__ __launch_bounds__(kLaneBlock) void k_tan_reverse(const double* __rest
       Cb[q] = cbar[(long)q * ld + li];
       Cbd[q] = cbard[(long)q * ld + li];
     }
-    L::template rev_tan<G>(M, Md, Cb, Cbd, mbd);
+    L::template rev_tan<P, double>(M, Md, Cb, Cbd, LaneRows<double>{mbard, lo}, ld);
   }
-#pragma unroll
-  for (int e = 0; e < NG; ++e) mbard[(long)(LO + e) * ld + li] = mbd[e];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -752,11 +782,11 @@ struct AdjImpl {
     hipLaunchKernelGGL((k_tan_forward<L>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, i0, n, a.perm, a.cfg,
                        a.ebar, xi, ebar, out, cbard);
   }
-  template <int G>
+  template <int P>
   static void tan_reverse_g(const double* m, const double* md, long ld, int n, const double* cb,
                             const double* cbd, double* mbd, hipStream_t s) {
     const int nb = (n + kLaneBlock - 1) / kLaneBlock;
-    hipLaunchKernelGGL((k_tan_reverse<L, G>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, n, cb, cbd, mbd);
+    hipLaunchKernelGGL((k_tan_reverse<L, P>), dim3(nb), dim3(kLaneBlock), 0, s, m, md, ld, n, cb, cbd, mbd);
   }
   template <int G>
   static void adj_pairs_g(const SysArgs& a, const double* fbar, int i0, int n, const double* mb,
@@ -794,6 +824,8 @@ struct AdjImpl {
     o.adj_pairs = &adj_pairs;
     o.nagroup = L::NAGROUP;
     o.ntgroup = L::NTGROUP;
+    o.nrtpart = L::NRTPART;
+    static_assert(L::NRTPART <= kMaxRevParts, "reverse-tangent parts");
     return o;
   }
 };

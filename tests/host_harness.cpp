@@ -95,6 +95,15 @@ static void adj_pair_groups(const double* mb, const double* mbd, double x, doubl
   }
 }
 
+// every part of the reverse-tangent program, in order, into one output vector
+template <int P>
+static void rev_tan_parts(const double* m, const double* md, const double* Cb, const double* Cbd, double* out) {
+  if constexpr (P < L::NRTPART) {
+    L::rev_tan<P, double>(RegM{m}, RegM{md}, Cb, Cbd, out, 1);
+    rev_tan_parts<P + 1>(m, md, Cb, Cbd, out);
+  }
+}
+
 int main() {
   const int np = 6;
   std::vector<double> d(3 * np), dl(3 * np);
@@ -159,26 +168,25 @@ int main() {
     for (int e = 0; e < L::NMOM; ++e) { mpl[e] = m[e] + h * md[e]; mmi[e] = m[e] - h * md[e]; }
     for (int q = 0; q < L::NCOMP; ++q) { cbp[q] = Cb[q] + h * Cbd[q]; cbm[q] = Cb[q] - h * Cbd[q]; }
     std::vector<double> rp(L::NMOM, 0.0), rm(L::NMOM, 0.0);
+    // the parts store or add their entries; poison mbd first so that a missed store shows
+    for (auto& v : mbd) v = 1e300;
+    rev_tan_parts<0>(m.data(), md.data(), Cb.data(), Cbd.data(), mbd.data());
     for (int g = 0; g < L::NGROUP; ++g) {
       const int lo = L::GROUP_LO[g];
-      double* outp = mbd.data() + lo;
       double* pp = rp.data() + lo;
       double* pm = rm.data() + lo;
       if (g == 0) {
-        L::rev_tan<0>(RegM{m.data()}, RegM{md.data()}, Cb.data(), Cbd.data(), outp);
         L::rev<0>(RegM{mpl.data()}, cbp.data(), pp);
         L::rev<0>(RegM{mmi.data()}, cbm.data(), pm);
       }
 #if MTP_NGROUP > 1
       if (g == 1) {
-        L::rev_tan<1>(RegM{m.data()}, RegM{md.data()}, Cb.data(), Cbd.data(), outp);
         L::rev<1>(RegM{mpl.data()}, cbp.data(), pp);
         L::rev<1>(RegM{mmi.data()}, cbm.data(), pm);
       }
 #endif
 #if MTP_NGROUP > 2
       if (g == 2) {
-        L::rev_tan<2>(RegM{m.data()}, RegM{md.data()}, Cb.data(), Cbd.data(), outp);
         L::rev<2>(RegM{mpl.data()}, cbp.data(), pp);
         L::rev<2>(RegM{mmi.data()}, cbm.data(), pm);
       }

@@ -17,10 +17,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="no host compiler")
-@pytest.mark.parametrize("level,groups", [(6, 1), (10, 1), (10, 2), (12, 3), (14, 1), (14, 2)])
-def test_generated_tangents_match_differences(tmp_path, level, groups):
+@pytest.mark.parametrize("level,groups,budget", [(6, 1, None), (10, 1, None), (10, 2, None), (12, 3, None),
+                                                 (14, 1, None), (14, 2, None), (12, 1, 140), (14, 2, 200)])
+def test_generated_tangents_match_differences(tmp_path, level, groups, budget):
+    """budget: a register budget small enough to cut the reverse-tangent program into several
+    parts (stores of first touches, additions of later ones, zeros of untouched entries)."""
     hdr = tmp_path / f"L{level}.inc"
-    hdr.write_text(emit_level(level, groups))
+    text = emit_level(level, groups) if budget is None else emit_level(level, groups, rtan_budget=budget)
+    if budget is not None:
+        assert int(text.split("NRTPART = ")[1].split(";")[0]) > 1, "budget too large for a split"
+    hdr.write_text(text)
     exe = tmp_path / "harness"
     cmd = ["g++", "-O1", "-std=c++17", f'-DMTP_LEVEL_HEADER="{hdr}"', f"-DMTP_LEVEL_STRUCT=Lv{level}",
            f"-DMTP_NGROUP={groups}", os.path.join(HERE, "host_harness.cpp"), "-o", str(exe)]

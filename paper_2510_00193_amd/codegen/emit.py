@@ -521,7 +521,7 @@ def emit_level(level: int, n_groups: int = 1, rtan_budget: int = RTAN_REG_BUDGET
     w("static constexpr int AMU_LO[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[0]][0]) for g in agroups) + "};")
     w("static constexpr int AMU_HI[NAGROUP] = {" + ", ".join(str(prog.layout.items[g[1] - 1][0]) for g in agroups) + "};")
     # ranges of the moment-tangent kernel
-    tgroups = tangent_moment_groups(groups, agroups)
+    tgroups = tangent_moment_groups(groups, agroups, prog.level)
     rparts = rev_tan_parts(prog, rtan_budget)
     # parts of the reverse-tangent program, run in order (one kernel each)
     w(f"static constexpr int NRTPART = {len(rparts)};")
@@ -993,15 +993,30 @@ def _emit_tangent_dispatchers(w: _W, n_rtparts: int, n_agroups: int, n_tgroups: 
         w("}")
 
 
-def tangent_moment_groups(groups, agroups):
+# Extra cuts of the chain's groups for the moment-tangent kernel, by level.  Measured at level
+# 20: the second group (entries 98-196, the higher-order moments) spilled 208 bytes per lane
+# in that kernel and took 2.6 ms of the batch step; cut at entry 148, its two passes take 1.85.
+TANGENT_EXTRA_CUTS = {20: (148,)}
+
+
+def tangent_moment_groups(groups, agroups, level=None):
     """Ranges of the moment-tangent kernel: the adjoint ranges where the chain has one group
     (its whole layout does not fit in registers next to the tangent monomials), else the
-    chain's groups (measured faster at level 20 than seven passes over the pairs)."""
-    return agroups if len(groups) == 1 else groups
+    chain's groups (measured faster at level 20 than seven passes over the pairs), cut further
+    at the level's extra cuts."""
+    if len(groups) == 1:
+        return agroups
+    cuts = TANGENT_EXTRA_CUTS.get(level, ())
+    out = []
+    for lo, hi in groups:
+        inner = sorted(c for c in cuts if lo < c < hi)
+        bounds = [lo] + inner + [hi]
+        out += [(bounds[k], bounds[k + 1]) for k in range(len(bounds) - 1)]
+    return out
 
 
 def emit_tangent_parts(w: _W, prog: Program, groups, agroups, rparts):
-    tgroups = tangent_moment_groups(groups, agroups)
+    tgroups = tangent_moment_groups(groups, agroups, prog.level)
     _emit_tangent_pair_functions(w, prog, tgroups)
     _emit_adj_pair_functions(w, prog, agroups)
     _emit_components_forward_tangent(w, prog)

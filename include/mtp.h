@@ -72,7 +72,8 @@ typedef struct {
   int precision;         /* MTP_FP64 or MTP_FP32_MOMENTS */
   int chunk_atoms;       /* atoms evaluated per chunk (bounds workspace, cf. the paper's
                             chunksize, Section 2.3); 0 = library default (1,048,576 atoms,
-                            about 2 KB of workspace per atom at level 16) */
+                            about 2 KB of workspace per atom at level 16); at most 2^28,
+                            else MTP_ERR_ARG */
   double grade_select;   /* grade_max above this returns MTP_GRADE_SELECT; <= 0 disables */
   double grade_break;    /* grade_max above this returns MTP_GRADE_BREAK; <= 0 disables */
   int lanes_per_atom;    /* lanes that share one atom's neighbour loop in the binary64 pair

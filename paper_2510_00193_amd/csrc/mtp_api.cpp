@@ -187,7 +187,7 @@ int mtp_create(const mtp_params* p, mtp_model** out) {
   if (!p->radial || !p->linear || !p->shift) return mtp_fail(MTP_ERR_ARG, "null coefficients");
   if (p->precision != MTP_FP64 && p->precision != MTP_FP32_MOMENTS)
     return mtp_fail(MTP_ERR_ARG, "unknown precision");
-  if (p->chunk_atoms < 0) return mtp_fail(MTP_ERR_ARG, "chunk_atoms < 0");
+  if (p->chunk_atoms < 0 || p->chunk_atoms > kMaxChunk) return mtp_fail(MTP_ERR_ARG, "chunk_atoms outside [0, 2^28]");
   if (p->lanes_per_atom != 0 && p->lanes_per_atom != 1 && p->lanes_per_atom != 2 && p->lanes_per_atom != 4 &&
       p->lanes_per_atom != 8)
     return mtp_fail(MTP_ERR_ARG, "lanes_per_atom must be 0, 1, 2, 4 or 8");

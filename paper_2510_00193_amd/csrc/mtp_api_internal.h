@@ -9,6 +9,7 @@
 #include "mtp.h"
 #include "mtp_internal.h"
 
+constexpr int kMaxChunk = 1 << 28;  // atoms per chunk at most: per-lane byte offsets in a row fit 32 bits
 constexpr int kDefaultChunk = 1 << 20;  // atoms per chunk: bounds the per-atom workspace (~2 KB/atom at level 16)
 constexpr int kLaneBlockHost = 64;     // workgroup size of the lane-per-atom kernels
 constexpr int kMaxAllPairsAtoms = 200000;  // largest system searched pair by pair (thin cells)

@@ -76,7 +76,9 @@ static void inv3(const double* H, double* I, double* det) {
   I[6] = C * id; I[7] = -(a * h - b * g) * id; I[8] = (a * e - b * d) * id;
 }
 
-static long chunk_of(const mtp_batch* b) { return std::max(1, std::min(b->chunk > 0 ? b->chunk : b->n, b->n)); }
+static long chunk_of(const mtp_batch* b) {
+  return std::max(1, std::min(std::min(b->chunk > 0 ? b->chunk : b->n, b->n), kMaxChunk));
+}
 
 // Reserve every buffer the run needs for the current schedule (never called during capture).
 static int reserve_run(mtp_batch* b) {

@@ -78,6 +78,7 @@ inline int pair_grid(const SysArgs& a, int nb) { return a.queue ? std::max(1, st
 // whole wave (scalar registers) and each lane adds its byte offset, so a load takes the
 // scalar-base form: no per-row 64-bit address is kept in vector registers (the compiler
 // otherwise precomputes the addresses of every row a program reads and spills them).
+// The host caps a chunk (the atoms of one row) at 2^28, so the byte offset fits 32 bits.
 __device__ __forceinline__ unsigned lane_bytes(int li, int size) { return (unsigned)li * (unsigned)size; }
 
 // Moment vector of a lane, [entry][atom] layout.

@@ -99,3 +99,6 @@ def test_lanes_per_atom_is_validated():
     for bad in (3, -1, 16):
         with pytest.raises(MtpError):
             _pot(p, lanes_per_atom=bad)
+    # chunks are capped so that a lane's byte offset in a row fits 32 bits
+    with pytest.raises(MtpError):
+        _pot(p, chunk_atoms=(1 << 28) + 1)

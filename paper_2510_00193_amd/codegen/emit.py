@@ -300,10 +300,11 @@ PREFETCH_DEPTH = int(os.environ.get("MTP_PREFETCH_DEPTH", "24"))
 TAN_PREFETCH_DEPTH = int(os.environ.get("MTP_TAN_PREFETCH_DEPTH", "24"))
 
 # Register estimate (VGPRs) of the reverse tangent of one block: values, tangents, adjoints and
-# adjoint tangents of its temporaries, plus the prefetched loads.  A part of the reverse-tangent
-# program holds the accumulators of its entries (two VGPRs each) next to its largest block;
-# parts are cut so that this stays within RTAN_REG_BUDGET (the 512 VGPR + AGPR of one wave per
-# SIMD, measured to spill little at this estimate).
+# adjoint tangents of its temporaries, the values and tangents of the entries it reads, and the
+# prefetched loads.  A part of the reverse-tangent program adds the accumulators live at each of
+# its blocks (two VGPRs each); parts are cut so that this stays within RTAN_REG_BUDGET (the 512
+# VGPR + AGPR of one wave per SIMD).  The estimate is rough (some parts spill, some blocks over
+# it do not); at level 20 budgets of 430, 512 and 545 measured 8.9, 8.1 and 8.05 ms.
 RTAN_REG_BUDGET = int(os.environ.get("MTP_RTAN_BUDGET", "512"))
 # blocks tried for each addition to a part (those adding the fewest new entries)
 RTAN_CANDIDATES = 12

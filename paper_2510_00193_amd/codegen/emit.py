@@ -65,8 +65,9 @@ def entry_groups(prog: Program, n_groups):
 
 # Most moment entries one adjoint pair group holds: the pair kernel of the parameter adjoint
 # keeps the adjoint and its tangent of every entry of its group in registers, next to the
-# per-lane radial-gradient sums of the group's mu values.
-ADJ_GROUP_CAP = 48
+# per-lane radial-gradient sums of the group's mu values (64: no spills at levels 16 and 20,
+# one pass fewer than 48 at level 20; 100 spills).
+ADJ_GROUP_CAP = 64
 
 
 def adj_entry_groups(prog: Program, cap=ADJ_GROUP_CAP):

@@ -813,8 +813,8 @@ def _rtan_peak(blk):
 
 def _rtan_live(order):
     """Register estimate of a part whose blocks run in the given order: an entry's accumulator
-    lives from the first block of the part that touches it to the last one (it is stored right
-    after that block), next to the block's own need."""
+    lives from the first block of the part that touches it to the last one (where it is stored
+    after its last update), next to the block's own need."""
     first, last = {}, {}
     for i, b in enumerate(order):
         for e in b.entries:
